@@ -1,0 +1,219 @@
+/*
+ * libfem — HEX8 finite-element hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every function returns an int status (FEM_OK = 0, negative codes
+ * below); no C++ exception or abort crosses this boundary.  The message of the
+ * last failure on the calling thread is available from fem_last_error().
+ *
+ * Problem solved (paper, Sec. 2.1): find u with u = u_D on the Dirichlet set and
+ *     C(u; theta) = R_int(u; theta) - F_ext = 0            (Eq. (weak), discretised)
+ * where R_int[(a,i)] = sum_e int_{Omega_e} f(grad u_h) : grad phi_(a,i) over HEX8
+ * elements with 2x2x2 Gauss quadrature, and f is one of
+ *   FEM_POISSON         f = m * grad u                         (scalar, ndpn = 1)
+ *   FEM_LINEAR_ELASTIC  f = lambda tr(eps) I + 2 mu eps, E = m  (Sec. 2.3, Eq. (linear_elasticity))
+ *   FEM_NEO_HOOKEAN     f = P = dW/dF, G = m, kappa = bulk_ratio * m  (Sec. 2.3, Eq. (neo-hookean))
+ * with a per-element modulus m(theta_e): theta_e itself (FEM_THETA_IDENTITY) or the
+ * SIMP map emin + theta_e^p (e0 - emin) (FEM_THETA_SIMP, Sec. 3.3, Eq. (top_weak)).
+ *
+ * Conventions shared with callers:
+ *   - HEX8 local node order 0:(0,0,0) 1:(1,0,0) 2:(1,1,0) 3:(0,1,0) 4:(0,0,1)
+ *     5:(1,0,1) 6:(1,1,1) 7:(0,1,1) in the reference cube;
+ *   - dof = ndpn * node + component (node-major, interleaved components);
+ *   - the global matrix is CSR over ALL dofs (Dirichlet dofs included), row i
+ *     holding every dof j that shares an element with i, columns ascending;
+ *   - Dirichlet dofs are eliminated symmetrically: residual entry 0, matrix row
+ *     and column replaced by the unit vector (so K stays symmetric for every
+ *     model here and the adjoint solve uses the same matrix).
+ *
+ * Memory ownership: all arrays passed to calls other than fem_build_pattern are
+ * DEVICE pointers owned by the caller (e.g. torch tensors on the same GPU) and
+ * must stay valid until the call's work on `stream` has finished.  The handle
+ * owns its own device copies of the mesh and the sparsity structure (allocated
+ * in fem_build_pattern, released by fem_destroy).  Scratch memory for assembly
+ * and solves is a caller-provided device `workspace` of fem_workspace_bytes().
+ * `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define FEM_OK 0
+#define FEM_EINVAL (-1)     /* bad argument (null pointer, size, enum value, mesh index) */
+#define FEM_ERANGE (-2)     /* pattern too large for 32-bit column indices / slots */
+#define FEM_EHIP (-3)       /* HIP runtime error */
+#define FEM_EMESH (-4)      /* det(dx/dxi) <= 0 at a Gauss point */
+#define FEM_EINVERTED (-5)  /* det(F) <= 0 at a Gauss point (neo-Hookean) */
+#define FEM_ENAN (-6)       /* NaN or Inf in a residual, tangent or Krylov scalar */
+#define FEM_EBREAKDOWN (-7) /* Krylov breakdown (rho or omega or p.Ap vanished) */
+#define FEM_EMAXITER (-8)   /* Newton or Krylov iteration limit reached */
+#define FEM_EDIVERGED (-9)  /* Newton residual grew beyond the divergence limit */
+#define FEM_ENOMEM (-10)    /* device allocation failed or workspace too small */
+
+/* ---------------------------------------------------------------- enumerations */
+enum { FEM_POISSON = 0, FEM_LINEAR_ELASTIC = 1, FEM_NEO_HOOKEAN = 2 };
+enum { FEM_THETA_IDENTITY = 0, FEM_THETA_SIMP = 1 };
+enum { FEM_F32 = 0, FEM_F64 = 1 };
+/* FEM_PREC_FP64: tangent, SpMV and Krylov vectors in FP64.
+ * FEM_PREC_MIXED: tangent values, SpMV and Krylov vectors in FP32 with FP32
+ * accumulation; the Newton/refinement residual, the adjoint refinement residual
+ * and all Krylov inner products stay FP64. */
+enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
+enum { FEM_KRYLOV_CG = 0, FEM_KRYLOV_BICGSTAB = 1 };
+
+typedef struct fem_handle fem_handle;
+
+/* Mesh, material and loads.  HOST pointers; copied by fem_build_pattern. */
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_elems;
+    int32_t ndpn;              /* 1 for FEM_POISSON, 3 otherwise */
+    int32_t model;             /* FEM_POISSON / FEM_LINEAR_ELASTIC / FEM_NEO_HOOKEAN */
+    int32_t pmap;              /* FEM_THETA_IDENTITY / FEM_THETA_SIMP */
+    int32_t reserved;
+    double nu;                 /* Poisson ratio (linear elasticity) */
+    double bulk_ratio;         /* kappa / G (neo-Hookean) */
+    double simp_p, simp_emin, simp_e0;
+    const double *coords;      /* [n_nodes * 3] */
+    const int32_t *conn;       /* [n_elems * 8], HEX8 local order above */
+    const uint8_t *dirichlet_mask; /* [n_nodes * ndpn], 1 = Dirichlet dof; may be NULL */
+    const double *f_nodal;     /* [n_nodes * ndpn] nodal point loads; may be NULL */
+    const double *source_nodal;/* [n_nodes * ndpn] body source b given at the nodes and
+                                  interpolated with the shape functions; may be NULL */
+    int64_t n_traction_faces;
+    const int32_t *traction_faces; /* [n_traction_faces * 2]: (element, local face);
+                                      local face = 2*axis + side, the face where the
+                                      reference coordinate xi_axis = -1 (side 0) or +1 */
+    const double *traction;        /* [n_traction_faces * ndpn] constant traction per face */
+} fem_mesh_desc;
+
+typedef struct {
+    int32_t precision;      /* FEM_PREC_FP64 or FEM_PREC_MIXED */
+    int32_t krylov;         /* FEM_KRYLOV_CG (SPD tangents) or FEM_KRYLOV_BICGSTAB */
+    int32_t n_load_steps;   /* >= 1 */
+    int32_t newton_max_it;  /* per load step */
+    double newton_rtol;     /* relative Newton tolerance (see fem_newton_solve) */
+    double newton_atol;
+    double krylov_rtol;     /* inner tolerance of each correction solve (recursive residual) */
+    int32_t krylov_max_it;
+    int32_t check_every;    /* Krylov convergence is read back every this many iterations */
+    double adjoint_rtol;    /* adjoint stops when ||b - K lambda|| <= adjoint_rtol ||b|| (FP64) */
+    int32_t adjoint_max_refine; /* outer refinement sweeps of the adjoint solve (mixed) */
+    int32_t profile_spmv;   /* 1: time every Krylov SpMV launch with HIP events */
+    int32_t newton_fixed_its; /* > 0: run exactly this many Newton iterations per load step
+                                 (the first one being the lifted step), without a convergence test */
+    int32_t reserved;
+} fem_solve_opts;
+
+#define FEM_MAX_HIST 64
+typedef struct {
+    int32_t newton_its;       /* total over load steps */
+    int32_t load_steps;
+    int32_t krylov_its_total;
+    int32_t n_hist;           /* entries used in krylov_its[] / residual_hist[] */
+    double initial_residual;  /* ||r_free|| at the start of the last load step */
+    double final_residual;    /* ||r_free|| (Newton) or ||b - K lambda|| (adjoint) at exit */
+    double ms_residual, ms_assemble, ms_krylov, ms_vjp, ms_total;
+    int32_t spmv_calls;       /* SpMV launches timed when profile_spmv = 1 */
+    int32_t krylov_unconverged; /* correction solves that stopped before reaching krylov_rtol */
+    double spmv_ms_total;     /* their summed event durations */
+    int32_t krylov_its[FEM_MAX_HIST];     /* Krylov iterations of each correction solve */
+    double residual_hist[FEM_MAX_HIST];   /* ||r_free|| before each correction */
+    double krylov_relres[FEM_MAX_HIST];   /* final recursive ||r||/||b|| of each correction solve */
+} fem_solve_stats;
+
+/* Message of the last failure on this thread ("" if none).  Never NULL. */
+const char *fem_last_error(void);
+
+/* Fills *opts with defaults: FP64, BiCGSTAB, 1 load step, newton_max_it 30,
+ * newton_rtol 1e-10, atol 0, krylov_rtol 1e-6, krylov_max_it 20000,
+ * check_every 16, adjoint_rtol 1e-10, adjoint_max_refine 20, profile off,
+ * newton_fixed_its 0. */
+int fem_default_opts(fem_solve_opts *opts);
+
+/* Builds the handle: uploads the mesh, computes the external load vector
+ * (nodal + traction + interpolated source, Sec. 2.1 Eq. (weak)), and builds the
+ * CSR pattern of the dof graph and the element-to-CSR slot map that implements
+ * "Add K_e to K" of Sec. 2.2 Alg. 1 without atomics.  Synchronous; uses the
+ * current HIP device.  Writes the number of dofs N = n_nodes*ndpn and of stored
+ * entries.  Errors: FEM_EINVAL (bad sizes, node index out of range, model/ndpn
+ * mismatch), FEM_ERANGE (nnz >= 2^31), FEM_ENOMEM, FEM_EHIP. */
+int fem_build_pattern(const fem_mesh_desc *desc, fem_handle **out, int64_t *n_dofs, int64_t *nnz);
+
+/* Releases the handle and its device memory (NULL is accepted). */
+void fem_destroy(fem_handle *h);
+
+/* Copies the pattern into caller DEVICE buffers (any may be NULL):
+ *   row_ptr [N+1] int64, col_idx [nnz] int32 (ascending per row),
+ *   slot_map [n_elems * Nd * Nd] int32 with Nd = 8*ndpn: slot_map[(e*Nd + p)*Nd + q] is the
+ *     CSR position of (dof(e,p), dof(e,q)), p = ndpn*a + i;
+ *   diag_slot [N] int64: CSR position of (d, d);
+ *   transpose_perm [nnz] int32: CSR position of the transposed entry.
+ * Asynchronous on `stream`. */
+int fem_pattern_export(fem_handle *h, int64_t *row_ptr, int32_t *col_idx, int32_t *slot_map, int64_t *diag_slot,
+                       int32_t *transpose_perm, void *stream);
+
+/* Copies the external load vector F_ext [N] (FP64) into a caller device buffer. */
+int fem_load_vector(fem_handle *h, double *f_ext, void *stream);
+
+/* Workspace size in bytes for fem_newton_solve / fem_adjoint_vjp with `opts`, or,
+ * with opts == NULL, for fem_assemble with FP64 values (the largest assembly case). */
+int fem_workspace_bytes(fem_handle *h, const fem_solve_opts *opts, size_t *bytes);
+
+/* Residual and tangent at u (Sec. 2.2: R_e and K_e = dr_e/dU_e, Alg. 1 assembly):
+ *   residual [N] FP64 (may be NULL): r = R_int(u; theta) - F_ext, Dirichlet entries 0;
+ *   values [nnz] (may be NULL): K(u) in CSR order, FEM_F32 or FEM_F64, with the
+ *   symmetric Dirichlet elimination.  u [N] FP64, theta [n_elems] FP64.
+ * Blocks until the kernels finish and reports FEM_EMESH / FEM_EINVERTED / FEM_ENAN. */
+int fem_assemble(fem_handle *h, const double *u, const double *theta, double *residual, void *values,
+                 int32_t values_dtype, void *workspace, size_t workspace_bytes, void *stream);
+
+/* y = alpha * op(K) x + beta * y with op(K) = K or K^T (transpose != 0); values, x and
+ * y all of `dtype`; accumulation in that dtype.  With beta == 0, y is not read.
+ * Asynchronous on `stream`. */
+int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t transpose, const void *x, void *y,
+             double alpha, double beta, void *stream);
+
+/* Tangent-vector product y = K(u) v, matrix-free in FP64, with the same Dirichlet
+ * elimination as the assembled matrix (y_d = v_d on Dirichlet dofs, Dirichlet
+ * entries of v ignored elsewhere).  Asynchronous. */
+int fem_apply_tangent(fem_handle *h, const double *u, const double *theta, const double *v, double *y,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Newton's method (Sec. 2.1, Eq. (newton)) with incremental loading: load step k of
+ * n scales F_ext by k/n and moves the Dirichlet values from those found in u on
+ * entry to `dirichlet_values` [N] (read on Dirichlet dofs only).  The first iteration
+ * of a step carries the Dirichlet increment D through the tangent at the previous
+ * state (du_D = D, K_ff du_f = -r_f - K_fD D); every later iteration evaluates the
+ * FP64 residual, assembles K(u), solves K du = -r with the Jacobi-preconditioned
+ * Krylov method of opts (Sec. 5, item 2) and updates u.  A step stops when
+ * ||r_free|| <= max(newton_rtol * max(||first right-hand side||, ||F_k||), atol).  In
+ * FEM_PREC_MIXED the correction solve runs in FP32 and the FP64 residual of the next
+ * iteration performs the refinement.  u [N] FP64 is in/out.  Blocks; returns
+ * FEM_EMAXITER / FEM_EDIVERGED / FEM_EBREAKDOWN / FEM_EMESH / FEM_EINVERTED / FEM_ENAN
+ * on failure (u then holds the last iterate).  `stats` may be NULL. */
+int fem_newton_solve(fem_handle *h, double *u, const double *theta, const double *dirichlet_values,
+                     const fem_solve_opts *opts, fem_solve_stats *stats, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+/* Adjoint gradient (Sec. 3, Eq. (adjoint_PDE) and Eq. (adjoint_chain_simp)):
+ * solves (dC/du)^T lambda = dJdu with Dirichlet entries of the right-hand side set
+ * to 0, then writes vjp_theta[e] = -lambda^T dC/dtheta_e [n_elems] FP64.  u is the
+ * converged state.  lambda_out [N] may be NULL.  In FEM_PREC_MIXED the transposed
+ * solve runs in FP32 inside FP64 iterative refinement whose residual uses the
+ * matrix-free FP64 tangent.  Blocks. */
+int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *vjp_theta,
+                    double *lambda_out, const fem_solve_opts *opts, fem_solve_stats *stats, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEM_H */

@@ -299,10 +299,11 @@ def newton_solve(prob, theta=None, linear: str = "direct", rtol: float = 1e-12, 
     """Newton's method with incremental loading.
 
     Load step k of n scales the external load by k/n and moves the Dirichlet values
-    linearly from their initial to their final values.  The initial guess of each step
-    is the previous converged field with the new Dirichlet values written in.  Each
-    Newton iteration solves K(u) du = -r(u) (Eq. newton) with Dirichlet rows and
-    columns eliminated and stops when ||r|| <= rtol * max(||r_0||, ||F_k||).
+    linearly from their initial to their final values.  The first Newton iteration of
+    a step carries the Dirichlet increment D through the tangent at the previous
+    state (du = D on Dirichlet dofs, K_ff du_f = -r_f - K_fD D); later iterations
+    solve K(u) du = -r(u) (Eq. newton) with Dirichlet rows and columns eliminated.
+    A step stops when ||r|| <= rtol * max(||first right-hand side||, ||F_k||).
     """
     theta = prob.theta if theta is None else theta
     pat = Pattern(prob) if pat is None else pat
@@ -314,11 +315,20 @@ def newton_solve(prob, theta=None, linear: str = "direct", rtol: float = 1e-12, 
     n_steps = max(1, prob.n_load_steps)
     for k in range(1, n_steps + 1):
         lam = k / n_steps
-        u[mask] = uD0 + lam * (g - uD0)
+        D = np.zeros(prob.n_dofs)
+        D[mask] = uD0 + lam * (g - uD0) - u[mask]
         Fk = lam * F
         r = residual(prob, pat, u, theta, Fk)
-        ref = max(np.linalg.norm(r), np.linalg.norm(Fk))
-        steps = []
+        _, Kfull = assemble(prob, pat, u, theta, Fk, residual=False, eliminate=False)
+        rhs = -r - spmv(pat, Kfull, D)
+        rhs[mask] = 0.0
+        ref = max(np.linalg.norm(rhs), np.linalg.norm(Fk))
+        steps = [np.linalg.norm(rhs)]
+        if steps[0] > rtol * ref:
+            _, vals = assemble(prob, pat, u, theta, Fk, residual=False, matrix=True)
+            u += linear_solve(pat, vals, rhs, linear, rtol=krylov_rtol)
+        u += D
+        r = residual(prob, pat, u, theta, Fk)
         for it in range(max_it + 1):
             rn = np.linalg.norm(r)
             steps.append(rn)
@@ -327,8 +337,7 @@ def newton_solve(prob, theta=None, linear: str = "direct", rtol: float = 1e-12, 
             if it == max_it:
                 raise OracleError(-8, f"newton load step {k} (|r|={rn:.3e}, ref={ref:.3e})")
             _, vals = assemble(prob, pat, u, theta, Fk, residual=False, matrix=True)
-            du = linear_solve(pat, vals, -r, linear, rtol=krylov_rtol)
-            u += du
+            u += linear_solve(pat, vals, -r, linear, rtol=krylov_rtol)
             r = residual(prob, pat, u, theta, Fk)
         if history is not None:
             history.append(steps)

@@ -1,0 +1,271 @@
+// C ABI of libfem: argument checks, handle lifetime, error translation.
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "solver.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return FEM_OK;
+    } catch (const fem::Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return FEM_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return FEM_EINVAL;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return FEM_EINVAL;
+    }
+}
+
+void require(bool ok, const char *what) {
+    if (!ok) throw fem::Error(FEM_EINVAL, what);
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+void bind_device(const fem_handle *h) { FEM_HIP(hipSetDevice(h->device)); }
+
+void validate_opts(const fem_solve_opts *o) {
+    require(o != nullptr, "opts is NULL");
+    require(o->precision == FEM_PREC_FP64 || o->precision == FEM_PREC_MIXED, "opts.precision");
+    require(o->krylov == FEM_KRYLOV_CG || o->krylov == FEM_KRYLOV_BICGSTAB, "opts.krylov");
+    require(o->n_load_steps >= 1, "opts.n_load_steps must be >= 1");
+    require(o->newton_max_it >= 0 && o->krylov_max_it >= 1 && o->check_every >= 1, "opts iteration limits");
+    require(o->krylov_rtol > 0.0 && o->krylov_rtol < 1.0, "opts.krylov_rtol must be in (0, 1)");
+    require(o->newton_rtol >= 0.0 && o->newton_atol >= 0.0 && o->adjoint_rtol >= 0.0, "opts tolerances");
+    require(o->adjoint_max_refine >= 1, "opts.adjoint_max_refine must be >= 1");
+    require(o->newton_fixed_its >= 0, "opts.newton_fixed_its must be >= 0");
+}
+
+void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, size_t bytes) {
+    size_t need = fem::solve_workspace_bytes(h, o);
+    if (need > 0 && ws == nullptr) throw fem::Error(FEM_EINVAL, "workspace is NULL");
+    if (bytes < need)
+        throw fem::Error(FEM_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fem_last_error(void) { return g_last_error.c_str(); }
+
+int fem_default_opts(fem_solve_opts *o) {
+    return guarded([&] {
+        require(o != nullptr, "opts is NULL");
+        std::memset(o, 0, sizeof(*o));
+        o->precision = FEM_PREC_FP64;
+        o->krylov = FEM_KRYLOV_BICGSTAB;
+        o->n_load_steps = 1;
+        o->newton_max_it = 30;
+        o->newton_rtol = 1e-10;
+        o->newton_atol = 0.0;
+        o->krylov_rtol = 1e-6;
+        o->krylov_max_it = 20000;
+        o->check_every = 16;
+        o->adjoint_rtol = 1e-10;
+        o->adjoint_max_refine = 20;
+        o->profile_spmv = 0;
+        o->newton_fixed_its = 0;
+    });
+}
+
+int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs, int64_t *nnz) {
+    fem_handle *h = nullptr;
+    int rc = guarded([&] {
+        require(d != nullptr && out != nullptr, "desc and out must be non-NULL");
+        *out = nullptr;
+        require(d->n_nodes >= 0 && d->n_elems >= 0, "negative mesh size");
+        require(d->model == FEM_POISSON || d->model == FEM_LINEAR_ELASTIC || d->model == FEM_NEO_HOOKEAN, "model");
+        require(d->ndpn == (d->model == FEM_POISSON ? 1 : 3), "ndpn must be 1 for FEM_POISSON and 3 otherwise");
+        require(d->pmap == FEM_THETA_IDENTITY || d->pmap == FEM_THETA_SIMP, "pmap");
+        require(d->n_nodes < (int64_t(1) << 31) / 3, "too many nodes for 32-bit dof indices");
+        require(d->n_nodes == 0 || d->coords != nullptr, "coords is NULL");
+        require(d->n_elems == 0 || d->conn != nullptr, "conn is NULL");
+        require(d->n_traction_faces >= 0 && (d->n_traction_faces == 0 || (d->traction_faces && d->traction)),
+                "traction faces");
+        if (d->model == FEM_LINEAR_ELASTIC) require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
+        if (d->model == FEM_NEO_HOOKEAN) require(d->bulk_ratio > 0.0, "bulk_ratio must be > 0");
+        h = new fem_handle();
+        FEM_HIP(hipGetDevice(&h->device));
+        FEM_HIP(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device));
+        h->mat = fem::Material{d->model, d->pmap, d->nu, d->bulk_ratio, d->simp_p, d->simp_emin, d->simp_e0};
+        const int64_t N = d->n_nodes * d->ndpn;
+        // every node must belong to an element (otherwise its row has no diagonal)
+        {
+            std::vector<uint8_t> used(d->n_nodes, 0);
+            for (int64_t i = 0; i < d->n_elems * 8; ++i) {
+                require(d->conn[i] >= 0 && d->conn[i] < d->n_nodes, "connectivity references a missing node");
+                used[d->conn[i]] = 1;
+            }
+            for (int64_t n = 0; n < d->n_nodes; ++n) require(used[n], "a node belongs to no element");
+        }
+        h->m.coords = static_cast<double *>(fem::dev_alloc(h, d->n_nodes * 3 * sizeof(double)));
+        h->m.conn = static_cast<int32_t *>(fem::dev_alloc(h, d->n_elems * 8 * sizeof(int32_t)));
+        h->m.mask = static_cast<uint8_t *>(fem::dev_alloc(h, N));
+        if (d->n_nodes) FEM_HIP(hipMemcpy(h->m.coords, d->coords, d->n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice));
+        if (d->n_elems) FEM_HIP(hipMemcpy(h->m.conn, d->conn, d->n_elems * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
+        h->m.host_mask.assign(N, 0);
+        if (d->dirichlet_mask)
+            for (int64_t i = 0; i < N; ++i) h->m.host_mask[i] = d->dirichlet_mask[i] ? 1 : 0;
+        if (N) FEM_HIP(hipMemcpy(h->m.mask, h->m.host_mask.data(), N, hipMemcpyHostToDevice));
+        fem::build_load_vector(h, d);
+        fem::build_graph(h, d);
+        // SpMV group width: a power of two covering the typical node degree; FEM_SPMV_GROUP overrides it.
+        if (const char *gs = std::getenv("FEM_SPMV_GROUP")) {
+            int gv = std::atoi(gs);
+            if (gv == 4 || gv == 8 || gv == 16 || gv == 32) h->spmv_group = gv;
+        }
+        h->status = static_cast<int *>(fem::dev_alloc(h, sizeof(int)));
+        FEM_HIP(hipMemset(h->status, 0, sizeof(int)));
+        FEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->host_status), sizeof(int)));
+        FEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->host_scalar), sizeof(double)));
+        FEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->host_kry), fem::kScalarsHostBytes));
+        if (n_dofs) *n_dofs = h->g.N;
+        if (nnz) *nnz = h->g.nnz;
+        *out = h;
+    });
+    if (rc != FEM_OK && h) fem_destroy(h);
+    return rc;
+}
+
+void fem_destroy(fem_handle *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    for (auto &e : h->events) (void)hipEventDestroy(e);
+    for (void *p : h->allocations) (void)hipFree(p);
+    if (h->host_status) (void)hipHostFree(h->host_status);
+    if (h->host_scalar) (void)hipHostFree(h->host_scalar);
+    if (h->host_kry) (void)hipHostFree(h->host_kry);
+    delete h;
+}
+
+int fem_pattern_export(fem_handle *h, int64_t *row_ptr, int32_t *col_idx, int32_t *slot_map, int64_t *diag_slot,
+                       int32_t *transpose_perm, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        bind_device(h);
+        fem::launch_export(h, row_ptr, col_idx, slot_map, diag_slot, transpose_perm, as_stream(stream));
+    });
+}
+
+int fem_load_vector(fem_handle *h, double *f_ext, void *stream) {
+    return guarded([&] {
+        require(h != nullptr && f_ext != nullptr, "handle and f_ext must be non-NULL");
+        bind_device(h);
+        if (h->g.N)
+            FEM_HIP(hipMemcpyAsync(f_ext, h->m.fext, h->g.N * sizeof(double), hipMemcpyDeviceToDevice,
+                                   as_stream(stream)));
+    });
+}
+
+int fem_workspace_bytes(fem_handle *h, const fem_solve_opts *o, size_t *bytes) {
+    return guarded([&] {
+        require(h != nullptr && bytes != nullptr, "handle and bytes must be non-NULL");
+        if (o) validate_opts(o);
+        *bytes = fem::solve_workspace_bytes(h, o);
+    });
+}
+
+int fem_assemble(fem_handle *h, const double *u, const double *theta, double *residual, void *values,
+                 int32_t values_dtype, void *workspace, size_t workspace_bytes, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        require(values_dtype == FEM_F32 || values_dtype == FEM_F64, "values_dtype");
+        const bool work = h->g.N > 0 && (residual || values);
+        if (!work) return;
+        require(u != nullptr && theta != nullptr, "u and theta must be non-NULL");
+        check_workspace(h, nullptr, workspace, workspace_bytes);
+        bind_device(h);
+        hipStream_t s = as_stream(stream);
+        void *ke;
+        double *rscr;
+        fem::carve_assemble(h, workspace, workspace_bytes, &ke, &rscr, values_dtype);
+        fem::reset_status(h, s);
+        if (residual) fem::launch_residual(h, u, theta, 1.0, rscr, residual, s);
+        if (values) {
+            if (values_dtype == FEM_F32) fem::launch_tangent<float>(h, u, theta, static_cast<float *>(ke),
+                                                                     static_cast<float *>(values), s);
+            else fem::launch_tangent<double>(h, u, theta, static_cast<double *>(ke), static_cast<double *>(values), s);
+        }
+        fem::check_status(h, s);
+    });
+}
+
+int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t transpose, const void *x, void *y,
+             double alpha, double beta, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        require(dtype == FEM_F32 || dtype == FEM_F64, "dtype");
+        if (h->g.N == 0) return;
+        require(values && x && y, "values, x and y must be non-NULL");
+        bind_device(h);
+        if (dtype == FEM_F32)
+            fem::launch_spmv<float>(h, static_cast<const float *>(values), transpose, static_cast<const float *>(x),
+                                    static_cast<float *>(y), float(alpha), float(beta), as_stream(stream));
+        else
+            fem::launch_spmv<double>(h, static_cast<const double *>(values), transpose, static_cast<const double *>(x),
+                                     static_cast<double *>(y), alpha, beta, as_stream(stream));
+    });
+}
+
+int fem_apply_tangent(fem_handle *h, const double *u, const double *theta, const double *v, double *y,
+                      void *workspace, size_t workspace_bytes, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        if (h->g.N == 0) return;
+        require(u && theta && v && y, "u, theta, v and y must be non-NULL");
+        check_workspace(h, nullptr, workspace, workspace_bytes);
+        bind_device(h);
+        void *ke;
+        double *rscr;
+        fem::carve_assemble(h, workspace, workspace_bytes, &ke, &rscr, FEM_F64);
+        fem::launch_apply_tangent(h, u, theta, v, rscr, y, as_stream(stream));
+    });
+}
+
+int fem_newton_solve(fem_handle *h, double *u, const double *theta, const double *dirichlet_values,
+                     const fem_solve_opts *opts, fem_solve_stats *stats, void *workspace, size_t workspace_bytes,
+                     void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        validate_opts(opts);
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        if (h->g.N == 0) return;
+        require(u && theta && dirichlet_values, "u, theta and dirichlet_values must be non-NULL");
+        check_workspace(h, opts, workspace, workspace_bytes);
+        bind_device(h);
+        fem::newton_solve(h, u, theta, dirichlet_values, *opts, stats, workspace, workspace_bytes, as_stream(stream));
+    });
+}
+
+int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *vjp_theta,
+                    double *lambda_out, const fem_solve_opts *opts, fem_solve_stats *stats, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        validate_opts(opts);
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        if (h->g.N == 0) return;
+        require(u && theta && dJdu && vjp_theta, "u, theta, dJdu and vjp_theta must be non-NULL");
+        check_workspace(h, opts, workspace, workspace_bytes);
+        bind_device(h);
+        fem::adjoint_vjp(h, u, theta, dJdu, vjp_theta, lambda_out, *opts, stats, workspace, workspace_bytes,
+                         as_stream(stream));
+    });
+}
+
+}  // extern "C"

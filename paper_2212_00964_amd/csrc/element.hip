@@ -1,0 +1,595 @@
+// Element-level kernels for HEX8 meshes on gfx950.
+//
+// Work mapping: one element per group of 8 consecutive lanes, lane a <-> local
+// node a (so a 64-wide wavefront holds 8 elements and every cross-lane exchange
+// stays inside a wavefront).  At each of the 2x2x2 Gauss points the lanes of an
+// element build the isoparametric Jacobian and the displacement gradient by an
+// 8-lane butterfly sum (every lane ends with bit-identical values), then each lane
+// forms the quantities of its own node.  For the tangent, each lane accumulates the
+// 3 x 24 row block of K_e that belongs to its node; the shape-gradient data of the
+// other seven nodes come from LDS.
+//
+// Element outputs go to a per-element scratch area and are summed per node / per
+// CSR block by separate gather kernels: every global entry is written exactly once,
+// with no atomics on values and a fixed summation order (deterministic).
+//
+// Paper: element residual R_e and K_e = dr_e/dU_e (Sec. 2.2), constitutive laws
+// (Sec. 2.3, Eq. (linear_elasticity), Eq. (neo-hookean)), assembly (Alg. 1).
+#include "internal.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kElemsPerBlock = kThreads / 8;
+
+__device__ __forceinline__ int ref_sign(int a, int j) {
+    // reference coordinates of HEX8 node a: x = (a ^ (a >> 1)) & 1, y = (a >> 1) & 1, z = (a >> 2) & 1
+    int bit = (j == 0) ? ((a ^ (a >> 1)) & 1) : (j == 1 ? ((a >> 1) & 1) : ((a >> 2) & 1));
+    return bit ? 1 : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T det3(const T A[3][3]) {
+    return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+// B = A^{-T} (so that B g = A^{-T} g), given det(A) = d.
+template <typename T>
+__device__ __forceinline__ void inv_transpose3(const T A[3][3], T d, T B[3][3]) {
+    T id = T(1) / d;
+    B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) * id;
+    B[1][0] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+    B[2][0] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+    B[0][1] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) * id;
+    B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+    B[2][1] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+    B[0][2] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) * id;
+    B[1][2] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+    B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+}
+
+__device__ __forceinline__ double modulus(const Material &m, double theta) {
+    return m.pmap == FEM_THETA_SIMP ? m.simp_emin + pow(theta, m.simp_p) * (m.simp_e0 - m.simp_emin) : theta;
+}
+
+__device__ __forceinline__ double dmodulus(const Material &m, double theta) {
+    return m.pmap == FEM_THETA_SIMP ? m.simp_p * pow(theta, m.simp_p - 1.0) * (m.simp_e0 - m.simp_emin) : 1.0;
+}
+
+// Per-lane geometry at Gauss point q: physical gradient g of this lane's shape
+// function and the Jacobian determinant (identical in all 8 lanes).
+template <typename T>
+__device__ __forceinline__ T gp_geometry(int a, int q, const T X[3], T g[3]) {
+    const T gq = T(0.57735026918962576451);  // 1/sqrt(3)
+    T xi[3] = {(q & 1) ? gq : -gq, (q & 2) ? gq : -gq, (q & 4) ? gq : -gq};
+    T l[3], s[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        s[j] = T(ref_sign(a, j));
+        l[j] = T(0.5) * (T(1) + s[j] * xi[j]);
+    }
+    T dN[3] = {T(0.5) * s[0] * l[1] * l[2], T(0.5) * s[1] * l[0] * l[2], T(0.5) * s[2] * l[0] * l[1]};
+    T J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) J[i][j] = sum8(X[i] * dN[j]);
+    T d = det3(J);
+    T Bt[3][3];
+    inv_transpose3(J, d, Bt);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = Bt[i][0] * dN[0] + Bt[i][1] * dN[1] + Bt[i][2] * dN[2];
+    return d;
+}
+
+// Gradient of a nodal field (ND components) at the Gauss point: G[i][J] = sum_a U_a,i g_a,J.
+template <int ND, typename T>
+__device__ __forceinline__ void field_grad(const T U[ND], const T g[3], T G[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G[i][j] = (i < ND) ? sum8(U[i] * g[j]) : T(0);
+}
+
+// Neo-Hookean kinematic scalars at F = I + G.
+template <typename T>
+struct NHState {
+    T F[3][3], H[3][3];  // H = F^{-T}
+    T J, I1, c, alpha, beta, pcoef;
+};
+
+template <typename T>
+__device__ __forceinline__ bool nh_state(const T G[3][3], T mod, T bulk_ratio, NHState<T> &s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s.F[i][j] = G[i][j] + (i == j ? T(1) : T(0));
+    s.J = det3(s.F);
+    bool ok = s.J > T(0);
+    T J = ok ? s.J : T(1);
+    inv_transpose3(s.F, J, s.H);
+    T I1 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) I1 += s.F[i][j] * s.F[i][j];
+    s.I1 = I1;
+    T kappa = bulk_ratio * mod;
+    T cr = cbrt(J);
+    s.c = mod / (cr * cr);  // G J^{-2/3}
+    s.alpha = T(2.0 / 9.0) * s.c * I1 + kappa * (T(2) * J * J - J);
+    s.beta = s.c * I1 * T(1.0 / 3.0) - kappa * (J * J - J);
+    s.pcoef = kappa * J * (J - T(1)) - s.c * I1 * T(1.0 / 3.0);  // P g = c F g + pcoef H g
+    return ok;
+}
+
+template <typename T>
+__device__ __forceinline__ void matvec3(const T A[3][3], const T x[3], T y[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[i] = A[i][0] * x[0] + A[i][1] * x[1] + A[i][2] * x[2];
+}
+
+// Flux applied to this lane's shape gradient: out = f(G) g (the integrand of R_e
+// at one Gauss point, before the quadrature weight).  Returns false if det F <= 0.
+template <int MODEL, typename T>
+__device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][3], const T g[3], T out[3]) {
+    if constexpr (MODEL == FEM_POISSON) {
+        out[0] = mod * (G[0][0] * g[0] + G[0][1] * g[1] + G[0][2] * g[2]);
+        out[1] = out[2] = T(0);
+        return true;
+    } else if constexpr (MODEL == FEM_LINEAR_ELASTIC) {
+        T nu = T(m.nu);
+        T lam = mod * nu / ((T(1) + nu) * (T(1) - T(2) * nu)), mu = mod / (T(2) * (T(1) + nu));
+        T tr = G[0][0] + G[1][1] + G[2][2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            out[i] = lam * tr * g[i] + mu * ((G[i][0] + G[0][i]) * g[0] + (G[i][1] + G[1][i]) * g[1] +
+                                             (G[i][2] + G[2][i]) * g[2]);
+        return true;
+    } else {
+        NHState<T> s;
+        bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
+        T f[3], h[3];
+        matvec3(s.F, g, f);
+        matvec3(s.H, g, h);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[i] = s.c * f[i] + s.pcoef * h[i];
+        return ok;
+    }
+}
+
+// Directional derivative of the flux: out = (A : dG) g with A the tangent at G.
+template <int MODEL, typename T>
+__device__ __forceinline__ bool dflux_dot(const Material &m, T mod, const T G[3][3], const T dG[3][3], const T g[3],
+                                          T out[3]) {
+    if constexpr (MODEL != FEM_NEO_HOOKEAN) {
+        return flux_dot<MODEL, T>(m, mod, dG, g, out);  // linear laws
+    } else {
+        NHState<T> s;
+        bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
+        T HdF = T(0), FdF = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                HdF += s.H[i][j] * dG[i][j];
+                FdF += s.F[i][j] * dG[i][j];
+            }
+        T f[3], h[3], dFg[3], mv[3], Hm[3];
+        matvec3(s.F, g, f);
+        matvec3(s.H, g, h);
+        matvec3(dG, g, dFg);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) mv[k] = dG[0][k] * h[0] + dG[1][k] * h[1] + dG[2][k] * h[2];  // dF^T h
+        matvec3(s.H, mv, Hm);
+        T c23 = T(2.0 / 3.0) * s.c;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            out[i] = s.c * dFg[i] - c23 * (f[i] * HdF + h[i] * FdF) + s.alpha * h[i] * HdF + s.beta * Hm[i];
+        return ok;
+    }
+}
+
+struct ElemIds {
+    int64_t e;
+    int a, el;
+    bool valid;
+};
+
+__device__ __forceinline__ ElemIds elem_ids(int64_t Ne) {
+    ElemIds id;
+    id.a = threadIdx.x & 7;
+    id.el = threadIdx.x >> 3;
+    int64_t e = int64_t(blockIdx.x) * kElemsPerBlock + id.el;
+    id.valid = e < Ne;
+    id.e = id.valid ? e : Ne - 1;  // idle groups recompute the last element and store nothing
+    return id;
+}
+
+// Loads this lane's node.  Coordinates (and, with rel_u, the field) are taken
+// relative to local node 0 of the element, in FP64 before rounding to T: the
+// gradients are unchanged (the shape-function gradients sum to zero) but the
+// differences of nearby absolute values no longer cancel in T arithmetic.
+template <int ND, typename T>
+__device__ __forceinline__ void load_node(const double *coords, const int32_t *conn, const double *u,
+                                          const uint8_t *mask, const ElemIds &id, T X[3], T U[ND], bool rel_u) {
+    const int64_t n = conn[id.e * 8 + id.a];
+    const int64_t n0 = conn[id.e * 8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X[i] = T(coords[3 * n + i] - coords[3 * n0 + i]);
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+        const int64_t d = ND * n + i, d0 = ND * n0 + i;
+        const double ua = (u == nullptr || (mask && mask[d])) ? 0.0 : u[d];
+        const double u0 = (!rel_u || u == nullptr || (mask && mask[d0])) ? 0.0 : u[d0];
+        U[i] = T(ua - u0);
+    }
+}
+
+// ------------------------------------------------------------------ residual-type kernels
+enum { VEC_RESIDUAL = 0, VEC_JVP = 1, VEC_VJP = 2, VEC_LIFT = 3 };
+
+// VEC_RESIDUAL: scratch[e][a][i] = sum_q detJ f(grad u) g_a            (modulus m(theta_e))
+// VEC_JVP:      scratch[e][a][i] = sum_q detJ (A(grad u) : grad v) g_a  (v with Dirichlet dofs zeroed)
+// VEC_VJP:      g[e] = -m'(theta_e) sum_{a,i free} lam_a,i sum_q detJ f_unit(grad u) g_a
+// VEC_LIFT:     as VEC_JVP but with v used on every dof (v is nonzero on Dirichlet dofs only)
+template <int MODEL, int ND, int MODE>
+__global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const double *__restrict__ coords,
+                                                          const int32_t *__restrict__ conn,
+                                                          const uint8_t *__restrict__ mask, Material mat,
+                                                          const double *__restrict__ theta,
+                                                          const double *__restrict__ u,
+                                                          const double *__restrict__ v, double *__restrict__ out,
+                                                          int *status) {
+    ElemIds id = elem_ids(Ne);
+    double X[3], U[ND], W[ND];
+    load_node<ND, double>(coords, conn, u, nullptr, id, X, U, true);
+    if (MODE != VEC_RESIDUAL)
+        load_node<ND, double>(coords, conn, v, MODE == VEC_LIFT ? nullptr : mask, id, X, W, MODE != VEC_VJP);
+    double th = theta[id.e];
+    double mod = (MODE == VEC_VJP) ? 1.0 : modulus(mat, th);
+    double acc[3] = {0, 0, 0};
+    bool mesh_ok = true, mat_ok = true;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        double g[3];
+        double dJ = gp_geometry(id.a, q, X, g);
+        mesh_ok &= dJ > 0.0;
+        double G[3][3], o[3];
+        field_grad<ND>(U, g, G);
+        if (MODE == VEC_JVP || MODE == VEC_LIFT) {
+            double dG[3][3];
+            field_grad<ND>(W, g, dG);
+            mat_ok &= dflux_dot<MODEL, double>(mat, mod, G, dG, g, o);
+        } else {
+            mat_ok &= flux_dot<MODEL, double>(mat, mod, G, g, o);
+        }
+#pragma unroll
+        for (int i = 0; i < ND; ++i) acc[i] += dJ * o[i];
+    }
+    if (id.valid && id.a == 0 && (!mesh_ok || !mat_ok))
+        atomicOr(status, (!mesh_ok ? ST_MESH : 0) | (!mat_ok ? ST_INVERTED : 0));
+    if (MODE == VEC_VJP) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) s += W[i] * acc[i];
+        s = sum8(s);
+        if (id.valid && id.a == 0) out[id.e] = -dmodulus(mat, th) * s;
+    } else if (id.valid) {
+#pragma unroll
+        for (int i = 0; i < ND; ++i) out[(id.e * 8 + id.a) * ND + i] = acc[i];
+    }
+}
+
+// Sum element contributions per dof.
+// VEC_RESIDUAL: out[d] = sum - lf * F[d], 0 on Dirichlet dofs.
+// VEC_JVP:      out[d] = sum, v[d] on Dirichlet dofs.
+// VEC_LIFT:     out[d] = sum, 0 on Dirichlet dofs.
+template <int ND, int MODE>
+__global__ __launch_bounds__(256) void k_gather_vec(int64_t N, const int64_t *__restrict__ ne_ptr,
+                                                    const int32_t *__restrict__ ne_list,
+                                                    const double *__restrict__ scratch,
+                                                    const uint8_t *__restrict__ mask, const double *__restrict__ F,
+                                                    double lf, const double *__restrict__ v,
+                                                    double *__restrict__ out, int *status) {
+    int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (d >= N) return;
+    int64_t n = d / ND;
+    int i = int(d - n * ND);
+    double s = 0.0;
+    for (int64_t k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) s += scratch[int64_t(ne_list[k]) * ND + i];
+    double r;
+    if (mask && mask[d]) {
+        r = (MODE == VEC_JVP) ? v[d] : 0.0;
+    } else {
+        r = (MODE == VEC_RESIDUAL) ? s - lf * F[d] : s;
+    }
+    if (!isfinite(r)) atomicOr(status, ST_NAN);
+    out[d] = r;
+}
+
+// ------------------------------------------------------------------ tangent kernel
+// Lane a accumulates the row block K_e[(a,i), (b,k)] for all b, i, k and writes it to
+// scratch[((e*8 + a)*8 + b)*ND*ND + i*ND + k].
+template <int MODEL, int ND, typename T>
+__global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const double *__restrict__ coords,
+                                                              const int32_t *__restrict__ conn, Material mat,
+                                                              const double *__restrict__ theta,
+                                                              const double *__restrict__ u, T *__restrict__ ke,
+                                                              int *status) {
+    constexpr int NV = (MODEL == FEM_NEO_HOOKEAN) ? 9 : 3;  // per-node data shared through LDS
+    constexpr int ES = 8 * NV + 1;                          // padded element stride (bank spread)
+    __shared__ T lds[kElemsPerBlock * ES];
+    ElemIds id = elem_ids(Ne);
+    T X[3], U[ND];
+    load_node<ND, T>(coords, conn, MODEL == FEM_NEO_HOOKEAN ? u : nullptr, nullptr, id, X, U, true);
+    T mod = T(modulus(mat, theta[id.e]));
+    T K[8][ND][ND];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int i = 0; i < ND; ++i)
+#pragma unroll
+            for (int k = 0; k < ND; ++k) K[b][i][k] = T(0);
+    bool mesh_ok = true, mat_ok = true;
+    T *my = lds + id.el * ES + id.a * NV;
+    const T *el = lds + id.el * ES;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        T g[3];
+        T dJ = gp_geometry(id.a, q, X, g);
+        mesh_ok &= dJ > T(0);
+        if constexpr (MODEL == FEM_NEO_HOOKEAN) {
+            T G[3][3];
+            field_grad<ND>(U, g, G);
+            NHState<T> s;
+            mat_ok &= nh_state(G, mod, T(mat.bulk_ratio), s);
+            T f[3], h[3];
+            matvec3(s.F, g, f);
+            matvec3(s.H, g, h);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                my[i] = g[i];
+                my[3 + i] = f[i];
+                my[6 + i] = h[i];
+            }
+            __syncthreads();
+            T cw = dJ * s.c, c23 = T(2.0 / 3.0) * cw, aw = dJ * s.alpha, bw = dJ * s.beta;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const T *o = el + b * NV;
+                T gb[3] = {o[0], o[1], o[2]}, fb[3] = {o[3], o[4], o[5]}, hb[3] = {o[6], o[7], o[8]};
+                T sdot = cw * (g[0] * gb[0] + g[1] * gb[1] + g[2] * gb[2]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        T v = aw * h[i] * hb[k] + bw * hb[i] * h[k] - c23 * (f[i] * hb[k] + h[i] * fb[k]);
+                        if (i == k) v += sdot;
+                        K[b][i][k] += v;
+                    }
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) my[i] = g[i];
+            __syncthreads();
+            if constexpr (MODEL == FEM_LINEAR_ELASTIC) {
+                T nu = T(mat.nu);
+                T lw = dJ * mod * nu / ((T(1) + nu) * (T(1) - T(2) * nu)), mw = dJ * mod / (T(2) * (T(1) + nu));
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const T *o = el + b * NV;
+                    T gb[3] = {o[0], o[1], o[2]};
+                    T sdot = mw * (g[0] * gb[0] + g[1] * gb[1] + g[2] * gb[2]);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            T v = lw * g[i] * gb[k] + mw * g[k] * gb[i];
+                            if (i == k) v += sdot;
+                            K[b][i][k] += v;
+                        }
+                }
+            } else {
+                T w = dJ * mod;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const T *o = el + b * NV;
+                    K[b][0][0] += w * (g[0] * o[0] + g[1] * o[1] + g[2] * o[2]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (id.valid && id.a == 0 && (!mesh_ok || !mat_ok))
+        atomicOr(status, (!mesh_ok ? ST_MESH : 0) | (!mat_ok ? ST_INVERTED : 0));
+    if (id.valid) {
+        T *dst = ke + (id.e * 8 + id.a) * 8 * ND * ND;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int i = 0; i < ND; ++i)
+#pragma unroll
+                for (int k = 0; k < ND; ++k) dst[(b * ND + i) * ND + k] = K[b][i][k];
+    }
+}
+
+// CSR values from element blocks: thread (block kb, row component i) writes the ND
+// entries values[row_ptr[ND*n+i] + ND*j + k], k < ND, of block kb = (n, j-th
+// neighbour m), summing the contributing element blocks in element order, then
+// applies the symmetric Dirichlet elimination.
+template <int ND, typename T>
+__global__ __launch_bounds__(256) void k_gather_values(int64_t nnzb, const int64_t *__restrict__ node_ptr,
+                                                       const int32_t *__restrict__ node_nb,
+                                                       const int32_t *__restrict__ blk_row,
+                                                       const int64_t *__restrict__ blk_ptr,
+                                                       const int32_t *__restrict__ blk_src,
+                                                       const int64_t *__restrict__ row_ptr,
+                                                       const uint8_t *__restrict__ mask, const T *__restrict__ ke,
+                                                       T *__restrict__ values, int *status) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nnzb * ND) return;
+    int64_t kb = t / ND;
+    int i = int(t - kb * ND);
+    int64_t n = blk_row[kb];
+    int64_t m = node_nb[kb];
+    int64_t j = kb - node_ptr[n];
+    T acc[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = T(0);
+    for (int64_t s = blk_ptr[kb]; s < blk_ptr[kb + 1]; ++s) {
+        const T *src = ke + int64_t(blk_src[s]) * ND * ND + i * ND;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) acc[k] += src[k];
+    }
+    int64_t row = ND * n + i;
+    bool bad = false;
+    T *dst = values + row_ptr[row] + ND * j;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        int64_t col = ND * m + k;
+        T v = acc[k];
+        if (mask && (mask[row] || mask[col])) v = (row == col) ? T(1) : T(0);
+        bad |= !isfinite(v);
+        dst[k] = v;
+    }
+    if (bad) atomicOr(status, ST_NAN);
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(256) void k_extract_dinv(int64_t N, const int64_t *__restrict__ node_ptr,
+                                                      const int32_t *__restrict__ bdiag,
+                                                      const int64_t *__restrict__ row_ptr,
+                                                      const T *__restrict__ values, T *__restrict__ dinv,
+                                                      int *status) {
+    int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (d >= N) return;
+    int64_t n = d / ND;
+    int i = int(d - n * ND);
+    T v = values[row_ptr[d] + ND * (bdiag[n] - node_ptr[n]) + i];
+    if (!(v != T(0)) || !isfinite(v)) atomicOr(status, ST_NAN);
+    dinv[d] = T(1) / v;
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads - 1) / threads); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+#define FEM_DISPATCH_MODEL(h, CALL)                                                                  \
+    switch ((h)->mat.model) {                                                                        \
+    case FEM_POISSON: { constexpr int MODEL = FEM_POISSON; constexpr int ND = 1; CALL; break; }      \
+    case FEM_LINEAR_ELASTIC: { constexpr int MODEL = FEM_LINEAR_ELASTIC; constexpr int ND = 3; CALL; break; } \
+    default: { constexpr int MODEL = FEM_NEO_HOOKEAN; constexpr int ND = 3; CALL; break; }          \
+    }
+
+void launch_residual(const fem_handle *h, const double *u, const double *theta, double lf, double *scratch,
+                     double *r, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0) {
+        FEM_HIP(hipMemsetAsync(r, 0, g.N * sizeof(double), s));
+        return;
+    }
+    unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    FEM_DISPATCH_MODEL(h, {
+        hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_RESIDUAL>), dim3(gridE), dim3(kThreads), 0, s, g.Ne,
+                           h->m.coords, h->m.conn, h->m.mask, h->mat, theta, u, nullptr, scratch, h->status);
+        hipLaunchKernelGGL((k_gather_vec<ND, VEC_RESIDUAL>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N,
+                           g.ne_ptr, g.ne_list, scratch, h->m.mask, h->m.fext, lf, nullptr, r, h->status);
+    });
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_apply_tangent(const fem_handle *h, const double *u, const double *theta, const double *v,
+                          double *scratch, double *y, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0) {
+        FEM_HIP(hipMemcpyAsync(y, v, g.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    FEM_DISPATCH_MODEL(h, {
+        hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_JVP>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
+                           h->m.conn, h->m.mask, h->mat, theta, u, v, scratch, h->status);
+        hipLaunchKernelGGL((k_gather_vec<ND, VEC_JVP>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
+                           g.ne_list, scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
+    });
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_lift(const fem_handle *h, const double *u, const double *theta, const double *v, double *scratch,
+                 double *y, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0) return;
+    unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    FEM_DISPATCH_MODEL(h, {
+        hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_LIFT>), dim3(gridE), dim3(kThreads), 0, s, g.Ne,
+                           h->m.coords, h->m.conn, h->m.mask, h->mat, theta, u, v, scratch, h->status);
+        hipLaunchKernelGGL((k_gather_vec<ND, VEC_LIFT>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
+                           g.ne_list, scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
+    });
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_vjp(const fem_handle *h, const double *u, const double *theta, const double *lam, double *gout,
+                hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0) return;
+    unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    FEM_DISPATCH_MODEL(h, {
+        hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_VJP>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
+                           h->m.conn, h->m.mask, h->mat, theta, u, lam, gout, h->status);
+    });
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke, T *values, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0) {
+        FEM_HIP(hipMemsetAsync(values, 0, g.nnz * sizeof(T), s));
+        return;
+    }
+    unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    FEM_DISPATCH_MODEL(h, {
+        hipLaunchKernelGGL((k_element_tangent<MODEL, ND, T>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
+                           h->m.conn, h->mat, theta, u, ke, h->status);
+        hipLaunchKernelGGL((k_gather_values<ND, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s, g.nnzb,
+                           g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, h->m.mask, ke, values,
+                           h->status);
+    });
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.N == 0) return;
+    if (g.nd == 1)
+        hipLaunchKernelGGL((k_extract_dinv<1, T>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.node_ptr, g.bdiag,
+                           g.row_ptr, values, dinv, h->status);
+    else
+        hipLaunchKernelGGL((k_extract_dinv<3, T>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.node_ptr, g.bdiag,
+                           g.row_ptr, values, dinv, h->status);
+    FEM_HIP(hipGetLastError());
+}
+
+template void launch_tangent<float>(const fem_handle *, const double *, const double *, float *, float *, hipStream_t);
+template void launch_tangent<double>(const fem_handle *, const double *, const double *, double *, double *,
+                                     hipStream_t);
+template void launch_extract_dinv<float>(const fem_handle *, const float *, float *, hipStream_t);
+template void launch_extract_dinv<double>(const fem_handle *, const double *, double *, hipStream_t);
+
+}  // namespace fem

@@ -1,0 +1,174 @@
+// Internal declarations of libfem (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fem.h"
+
+namespace fem {
+
+// Error carried from deep inside the library up to the ABI wrapper.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define FEM_HIP(call)                                                                                        \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            throw ::fem::Error(e_ == hipErrorOutOfMemory ? FEM_ENOMEM : FEM_EHIP,                            \
+                               std::string(#call " failed: ") + hipGetErrorString(e_));                      \
+    } while (0)
+
+// Bits of the device status word raised by kernels.
+enum : int { ST_MESH = 1, ST_INVERTED = 2, ST_NAN = 4, ST_BREAKDOWN = 8 };
+
+// Material description passed by value to kernels.
+struct Material {
+    int model, pmap;
+    double nu, bulk_ratio, simp_p, simp_emin, simp_e0;
+};
+
+// Completion counters of the grid-wide reductions: a two-level tree with kFanIn
+// blocks per first-level counter and one counter per 128-byte line.
+constexpr int kFanIn = 32;
+constexpr int kCounterStride = 32;
+constexpr int kMaxReduceBlocks = 4096;
+constexpr int kCounterSlots = (kMaxReduceBlocks / kFanIn + 1) * kCounterStride;
+
+// Device-side Krylov scalars (FP64), one instance per solve in the workspace.
+struct KrylovScalars {
+    double rho, rho_old, alpha, omega, beta;
+    double bnorm2, rnorm2, tol2;
+    double rh2;      // |rhat|^2 (BiCGSTAB shadow residual)
+    double rmin2;    // smallest |r|^2 reached so far
+    int its, converged, breakdown;
+    int restart_at;  // BiCGSTAB restarts (rhat = p = r) at the iteration with this index
+    alignas(128) unsigned int counters[kCounterSlots];  // reduction completion tree (self-resetting)
+};
+// Bytes of KrylovScalars read back by the host (everything before the counters).
+constexpr size_t kScalarsHostBytes = offsetof(KrylovScalars, counters);
+
+// Sparsity structure on the device.  A "block" is the ndpn x ndpn coupling of a
+// node pair (n, m); blocks are numbered in CSR order of the node graph.
+struct Graph {
+    int64_t Nn = 0, Ne = 0, N = 0, nnz = 0, nnzb = 0;
+    int nd = 1;
+    int64_t *node_ptr = nullptr;  // [Nn+1] first block of node n
+    int32_t *node_nb = nullptr;   // [nnzb] neighbour node of each block, ascending per node
+    int32_t *blk_row = nullptr;   // [nnzb] owning node of each block
+    int32_t *mirror = nullptr;    // [nnzb] block (m, n) for block (n, m)
+    int32_t *bdiag = nullptr;     // [Nn] block (n, n)
+    int64_t *blk_ptr = nullptr;   // [nnzb+1] contributions of element-pair blocks
+    int32_t *blk_src = nullptr;   // [64*Ne] contribution e*64 + a*8 + b, element ascending
+    int64_t *ne_ptr = nullptr;    // [Nn+1] node -> (element, local node) incidence
+    int32_t *ne_list = nullptr;   // [8*Ne] e*8 + a, element ascending
+    int32_t *bslot = nullptr;     // [Ne*64] block of local pair (a, b) of element e
+    int64_t *row_ptr = nullptr;   // [N+1] scalar CSR row starts
+};
+
+// Problem mesh on the device.
+struct DeviceMesh {
+    double *coords = nullptr;  // [Nn*3]
+    int32_t *conn = nullptr;   // [Ne*8]
+    uint8_t *mask = nullptr;   // [N]
+    double *fext = nullptr;    // [N]
+    double fext_norm = 0.0;
+    std::vector<uint8_t> host_mask;
+};
+
+}  // namespace fem
+
+struct fem_handle {
+    int device = 0;
+    fem::Material mat{};
+    fem::Graph g;
+    fem::DeviceMesh m;
+    int *status = nullptr;                    // device status word (ST_* bits)
+    int *host_status = nullptr;               // pinned read-back slots
+    double *host_scalar = nullptr;
+    fem::KrylovScalars *host_kry = nullptr;
+    std::vector<hipEvent_t> events;           // SpMV timing events (profile_spmv)
+    int spmv_group = 16;                      // SpMV tuning knob (nodes in flight per lane group)
+    int num_cus = 256;                        // compute units of the device
+    std::vector<void *> allocations;          // device allocations owned by the handle
+};
+
+namespace fem {
+
+// ------------------------------------------------------------------ setup (host)
+void build_graph(fem_handle *h, const fem_mesh_desc *d);
+void build_load_vector(fem_handle *h, const fem_mesh_desc *d);
+void *dev_alloc(fem_handle *h, size_t bytes);
+
+// ------------------------------------------------------------------ element kernels
+// r_scratch: [Ne*8*nd] FP64 per (element, local node, component).
+void launch_residual(const fem_handle *h, const double *u, const double *theta, double load_factor,
+                     double *r_scratch, double *r_out, hipStream_t s);
+void launch_apply_tangent(const fem_handle *h, const double *u, const double *theta, const double *v,
+                          double *y_scratch, double *y_out, hipStream_t s);
+// ke_scratch: [Ne*64*nd*nd] of the value type; values [nnz].
+template <typename T>
+void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke_scratch, T *values,
+                    hipStream_t s);
+// y = (K(u) v) on free dofs with v used on every dof (Dirichlet lifting), 0 on Dirichlet dofs.
+void launch_lift(const fem_handle *h, const double *u, const double *theta, const double *v, double *scratch,
+                 double *y, hipStream_t s);
+void launch_vjp(const fem_handle *h, const double *u, const double *theta, const double *lam, double *g,
+                hipStream_t s);
+template <typename T>
+void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s);
+
+// ------------------------------------------------------------------ sparse / vector kernels
+template <typename T>
+void launch_spmv(const fem_handle *h, const T *values, int transpose, const T *x, T *y, T alpha, T beta,
+                 hipStream_t s);
+void launch_export(const fem_handle *h, int64_t *row_ptr, int32_t *col_idx, int32_t *slot, int64_t *diag,
+                   int32_t *tperm, hipStream_t s);
+
+// Fused Krylov kernels (grid-stride, FP64 reductions finished by the last block).
+int krylov_grid(const fem_handle *h);
+size_t krylov_partials_bytes(const fem_handle *h);
+
+template <typename T>
+struct KrylovVecs {
+    const T *A;  // CSR values of the operator
+    T *x, *r, *rh, *p, *v, *s, *t, *ph, *sh, *dinv;
+    double *partials;
+    KrylovScalars *sc;
+};
+
+template <typename T>
+void kry_bicg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
+template <typename T>
+void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
+template <typename T>
+void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
+template <typename T>
+void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
+
+// Vector helpers.
+void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, unsigned *counter,
+                       hipStream_t s);
+template <typename TO, typename TI>
+void launch_scale_cast(const TI *in, TO *out, double alpha, int64_t n, hipStream_t s);
+template <typename TI>
+void launch_axpy_to_f64(const TI *x, double *y, int64_t n, hipStream_t s);
+void launch_set_dirichlet(const fem_handle *h, double *u, const double *u0, const double *g, double lam,
+                          hipStream_t s);
+// delta = (u0 + lam (g - u0) - u) on Dirichlet dofs, 0 elsewhere
+void launch_dirichlet_increment(const fem_handle *h, const double *u, const double *u0, const double *g, double lam,
+                                double *delta, hipStream_t s);
+// out = -(a + b)
+void launch_neg_sum(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
+void launch_mask_copy(const fem_handle *h, const double *in, double *out, hipStream_t s);
+void launch_sub(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
+
+}  // namespace fem

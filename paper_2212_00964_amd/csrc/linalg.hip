@@ -1,0 +1,855 @@
+// Sparse matrix-vector products and Jacobi-preconditioned Krylov kernels.
+//
+// The CSR matrix is stored over all dofs with node-major interleaved components, so
+// the ND rows of node n are contiguous and each of them lists the node's neighbour
+// blocks in the same order.  The SpMV therefore walks the node graph (one 32-bit
+// column index per ND x ND block) instead of the scalar column array: a group of 32
+// lanes owns one node, lane l takes the l-th neighbour block, and the ND row sums
+// are finished with a 32-lane butterfly.
+//
+// Krylov kernels are persistent (a fixed grid of blocks walking contiguous node
+// ranges), so their FP64 inner products reduce deterministically: per-block partial
+// sums in a fixed lane order, then the last block to finish sums the partials in
+// block order and updates the scalars of the method on the device.  The host only
+// reads the convergence flag every few iterations.
+//
+// Paper: BiCGSTAB with a Jacobi preconditioner is the linear solver inside Newton
+// (Sec. 5, item 2; van der Vorst 1992).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads - 1) / threads); }
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// Row sums of node n: acc[i] = sum_j sum_k K[(n,i),(m_j,k)] x[(m_j,k)] (or K^T),
+// computed by a group of G lanes (lane l takes blocks l, l+G, ...).  Every lane of
+// the group returns the same totals.
+template <int ND, int G, bool TRANS, typename T>
+__device__ __forceinline__ void node_rows(int64_t n, int lane, const int64_t *__restrict__ node_ptr,
+                                          const int32_t *__restrict__ node_nb, const int32_t *__restrict__ mirror,
+                                          const T *__restrict__ values, const T *__restrict__ x, T acc[ND]) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) acc[i] = T(0);
+    const int64_t b0 = node_ptr[n];
+    const int deg = int(node_ptr[n + 1] - b0);
+    const T *vb = values + int64_t(ND) * ND * b0;
+#pragma unroll 4
+    for (int l = lane; l < deg; l += G) {
+        const int64_t m = node_nb[b0 + l];
+        T xm[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) xm[k] = x[ND * m + k];
+        if constexpr (!TRANS) {
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+                const T *row = vb + int64_t(i) * ND * deg + ND * l;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) acc[i] += __builtin_nontemporal_load(row + k) * xm[k];
+            }
+        } else {
+            // (K^T)[(n,i),(m,k)] = K[(m,k),(n,i)], stored in block (m, n) = mirror
+            const int64_t kb = mirror[b0 + l];
+            const int64_t mb0 = node_ptr[m];
+            const int mdeg = int(node_ptr[m + 1] - mb0);
+            const T *mv = values + int64_t(ND) * ND * mb0 + ND * (kb - mb0);
+#pragma unroll
+            for (int k = 0; k < ND; ++k)
+#pragma unroll
+                for (int i = 0; i < ND; ++i) acc[i] += mv[int64_t(k) * ND * mdeg + i] * xm[k];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < ND; ++i) acc[i] = group_sum<G>(acc[i]);
+}
+
+template <int ND, int G, bool TRANS, typename T>
+__global__ __launch_bounds__(kThreads) void k_spmv(int64_t Nn, const int64_t *__restrict__ node_ptr,
+                                                   const int32_t *__restrict__ node_nb,
+                                                   const int32_t *__restrict__ mirror, const T *__restrict__ values,
+                                                   const T *__restrict__ x, T *__restrict__ y, T alpha, T beta) {
+    const int lane = threadIdx.x % G;
+    const int64_t n = int64_t(blockIdx.x) * (kThreads / G) + threadIdx.x / G;
+    if (n >= Nn) return;  // uniform per group
+    T acc[ND];
+    node_rows<ND, G, TRANS, T>(n, lane, node_ptr, node_nb, mirror, values, x, acc);
+    if (lane < ND) {
+        T s = acc[0];
+#pragma unroll
+        for (int i = 1; i < ND; ++i)
+            if (lane == i) s = acc[i];
+        T out = alpha * s;
+        if (beta != T(0)) out += beta * y[ND * n + lane];
+        y[ND * n + lane] = out;
+    }
+}
+
+// ------------------------------------------------------------------ deterministic reductions
+// Per-thread values v[0..NV) are reduced over the block; thread 0 stores the block
+// totals to partials[c * gridDim.x + blockIdx.x].  Returns true in the (single) block
+// that finishes last; that block then sees every partial.  Completion is counted in
+// a two-level tree (kFanIn blocks per first-level counter, each counter on its own
+// 128-byte line) so that thousands of blocks never queue on one atomic address.
+__device__ __forceinline__ int counter_groups(unsigned G) { return int((G + kFanIn - 1) / kFanIn); }
+
+template <int NV>
+__device__ bool block_partials(const double v[NV], double *partials, unsigned int *counters) {
+    __shared__ double red[kThreads / 64][NV > 0 ? NV : 1];
+    __shared__ bool last;
+    double w[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double t = v[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        w[c] = t;
+    }
+    const int wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) red[wave][c] = w[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double t = 0.0;
+            for (int k = 0; k < kThreads / 64; ++k) t += red[k][c];
+            partials[c * gridDim.x + blockIdx.x] = t;
+        }
+        const unsigned G = gridDim.x;
+        const int ng = counter_groups(G);
+        const int grp = int(blockIdx.x / kFanIn);
+        const unsigned members = (unsigned(grp) == unsigned(ng - 1)) ? G - unsigned(grp) * kFanIn : unsigned(kFanIn);
+        bool top = false;
+        __threadfence();
+        unsigned prev = atomicAdd(&counters[grp * kCounterStride], 1u);
+        if (prev == members - 1) {
+            counters[grp * kCounterStride] = 0u;  // every member has arrived: reset for the next kernel
+            __threadfence();
+            unsigned p2 = atomicAdd(&counters[ng * kCounterStride], 1u);
+            top = (p2 == unsigned(ng - 1));
+            if (top) counters[ng * kCounterStride] = 0u;
+        }
+        last = top;
+    }
+    __syncthreads();
+    return last;
+}
+
+// Load that bypasses the per-CU vector L1 (other blocks wrote the value through L2).
+__device__ __forceinline__ double load_l2(const double *p) {
+    unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double(static_cast<long long>(v));
+}
+
+// Called by all threads of the last block: totals of every partial, in block order.
+template <int NV>
+__device__ void finish_partials(const double *partials, double tot[NV]) {
+    __shared__ double red[kThreads / 64][NV];
+    __threadfence();
+    double v[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double t = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += kThreads) t += load_l2(&partials[c * gridDim.x + b]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        v[c] = t;
+    }
+    const int wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) red[wave][c] = v[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double t = 0.0;
+        for (int k = 0; k < kThreads / 64; ++k) t += red[k][c];
+        tot[c] = t;
+    }
+}
+
+// Contiguous node range of this block.  Blocks are dealt round-robin to the 8 XCDs,
+// so the logical block index groups the blocks of one XCD onto adjacent ranges and
+// each XCD's L2 sees a compact slab of the mesh (the x-vector gathers stay local).
+__device__ __forceinline__ void block_range(int64_t Nn, int64_t &n0, int64_t &n1) {
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    const unsigned per = G / 8;
+    unsigned L = (G % 8 == 0) ? (b % 8) * per + b / 8 : b;
+    int64_t chunk = (Nn + G - 1) / G;
+    n0 = int64_t(L) * chunk;
+    n1 = n0 + chunk < Nn ? n0 + chunk : Nn;
+}
+
+__device__ __forceinline__ bool stopped(const KrylovScalars *sc) { return sc->converged | sc->breakdown; }
+
+// Persistent SpMV over this block's contiguous node range.  The range's row
+// pointers are staged in LDS once; each 32-lane group then takes P nodes at a time
+// and issues all their column-index and value loads before any of them is used, so
+// a wave keeps P times more HBM traffic in flight than a one-node-at-a-time walk.
+// Lane l of a group handles neighbour block l of each of its nodes (node degrees
+// above 32 fall back to a strided loop).
+//
+// MODE 0: y = alpha K x + beta y
+// MODE 1: y = K x and alpha = rho / (w0, y)                 (BiCGSTAB v = K ph, CG q = K p)
+// MODE 2: y = K x and omega = (w0, y) / (y, y), w0 = s      (BiCGSTAB t = K sh)
+constexpr int kSpmvGroup = 32;
+constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
+
+template <int ND, int P, int MODE, typename T>
+__global__ __launch_bounds__(kThreads) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
+                                                         const int32_t *__restrict__ node_nb,
+                                                         const T *__restrict__ values, const T *__restrict__ x,
+                                                         T *__restrict__ y, const T *__restrict__ w0, T alpha,
+                                                         T beta, double *partials, KrylovScalars *sc, int cg) {
+    constexpr int G = kSpmvGroup;
+    constexpr int GPB = kThreads / G;  // groups per block
+    __shared__ int64_t sptr[kMaxChunk + 1];
+    if (MODE != 0 && stopped(sc)) return;
+    int64_t r0, r1;
+    block_range(Nn, r0, r1);
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t n0 = r0; n0 < r1; n0 += kMaxChunk) {
+    const int cnt = int(r1 - n0 < kMaxChunk ? r1 - n0 : kMaxChunk);
+    __syncthreads();  // previous sub-chunk finished with sptr
+    for (int i = threadIdx.x; i <= cnt; i += kThreads) sptr[i] = node_ptr[n0 + i];
+    __syncthreads();
+    for (int base = grp; base < cnt; base += P * GPB) {
+        int64_t b0[P];
+        int deg[P];
+        int32_t m[P];
+        T v[P][ND][ND];
+        T xm[P][ND];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int ln = base + p * GPB;
+            const bool ok = ln < cnt;
+            b0[p] = ok ? sptr[ln] : 0;
+            deg[p] = ok ? int(sptr[ln + 1] - sptr[ln]) : 0;
+        }
+        // Loads are unconditional (inactive lanes read block 0 of their node, which
+        // always exists) so they stay branch-free and vectorised; results are masked.
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int lc = lane < deg[p] ? lane : 0;
+            m[p] = __builtin_nontemporal_load(node_nb + b0[p] + lc);
+            const T *vb = values + int64_t(ND) * ND * b0[p] + ND * lc;
+#pragma unroll
+            for (int i = 0; i < ND; ++i)
+#pragma unroll
+                for (int k = 0; k < ND; ++k) v[p][i][k] = __builtin_nontemporal_load(vb + int64_t(i) * ND * deg[p] + k);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < ND; ++k) xm[p][k] = x[int64_t(ND) * m[p] + k];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (!(lane < deg[p]))
+#pragma unroll
+                for (int k = 0; k < ND; ++k) xm[p][k] = T(0);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            T acc[ND];
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+                T a = T(0);
+#pragma unroll
+                for (int k = 0; k < ND; ++k) a += v[p][i][k] * xm[p][k];
+                acc[i] = lane < deg[p] ? a : T(0);
+            }
+            for (int l = lane + G; l < deg[p]; l += G) {  // high-degree nodes
+                const int64_t mm = node_nb[b0[p] + l];
+                const T *vb = values + int64_t(ND) * ND * b0[p] + ND * l;
+#pragma unroll
+                for (int i = 0; i < ND; ++i)
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) acc[i] += vb[int64_t(i) * ND * deg[p] + k] * x[ND * mm + k];
+            }
+#pragma unroll
+            for (int i = 0; i < ND; ++i) acc[i] = group_sum<G>(acc[i]);
+            const int ln = base + p * GPB;
+            if (ln < cnt && lane < ND) {
+                T sv = acc[0];
+#pragma unroll
+                for (int i = 1; i < ND; ++i)
+                    if (lane == i) sv = acc[i];
+                const int64_t d = int64_t(ND) * (n0 + ln) + lane;
+                if (MODE == 0) {
+                    T out = alpha * sv;
+                    if (beta != T(0)) out += beta * y[d];
+                    y[d] = out;
+                } else {
+                    y[d] = sv;
+                    d0 += double(w0[d]) * double(sv);
+                    if (MODE == 2) d1 += double(sv) * double(sv);
+                }
+            }
+        }
+    }
+    }
+    if constexpr (MODE != 0) {
+    double vv[2] = {d0, d1};
+    if (block_partials<MODE>(vv, partials, sc->counters)) {
+        double tot[MODE];
+        finish_partials<MODE>(partials, tot);
+        if (threadIdx.x == 0) {
+            if (MODE == 1) {
+                bool bad = !(tot[0] != 0.0) || !isfinite(tot[0]) || (cg && !(tot[0] > 0.0));
+                if (bad) sc->breakdown = 1;
+                else sc->alpha = sc->rho / tot[0];
+            } else {
+                double tt = tot[1];
+                if (!(tt > 0.0) || !isfinite(tt)) {
+                    sc->omega = 0.0;
+                } else {
+                    sc->omega = tot[0] / tt;
+                }
+            }
+        }
+    }
+    }
+}
+
+// BiCGSTAB: beta = (rho/rho_old)(alpha/omega); p = r + beta (p - omega v); ph = Dinv p.
+// On a restart iteration the shadow residual and the direction restart from r.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_p(int64_t N, const T *__restrict__ r, T *__restrict__ p,
+                                                     const T *__restrict__ v, T *__restrict__ ph,
+                                                     T *__restrict__ rh, const T *__restrict__ dinv,
+                                                     const KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const bool restart = sc->restart_at == sc->its;
+    const double beta = (sc->its == 0 || restart) ? 0.0 : (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
+    const T bt = T(beta), om = T(sc->omega);
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
+        T ri = r[i];
+        T pi = restart ? ri : ri + bt * (p[i] - om * v[i]);
+        p[i] = pi;
+        ph[i] = dinv[i] * pi;
+        if (restart) rh[i] = ri;
+    }
+}
+
+// BiCGSTAB: s = r - alpha v; sh = Dinv s
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t N, const T *__restrict__ r, const T *__restrict__ v,
+                                                     T *__restrict__ s, T *__restrict__ sh,
+                                                     const T *__restrict__ dinv, const KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const T al = T(sc->alpha);
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
+        T si = r[i] - al * v[i];
+        s[i] = si;
+        sh[i] = dinv[i] * si;
+    }
+}
+
+// BiCGSTAB: x += alpha ph + omega sh; r = s - omega t; rho_new = (rh, r); |r|^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t N, T *__restrict__ x, T *__restrict__ r,
+                                                      const T *__restrict__ rh, const T *__restrict__ ph,
+                                                      const T *__restrict__ s, const T *__restrict__ sh,
+                                                      const T *__restrict__ t, double *partials, KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const T al = T(sc->alpha), om = T(sc->omega);
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
+        x[i] += al * ph[i] + om * sh[i];
+        T ri = s[i] - om * t[i];
+        r[i] = ri;
+        d0 += double(rh[i]) * double(ri);
+        d1 += double(ri) * double(ri);
+    }
+    double v[2] = {d0, d1};
+    if (block_partials<2>(v, partials, sc->counters)) {
+        double tot[2];
+        finish_partials<2>(partials, tot);
+        if (threadIdx.x == 0) {
+            sc->rho_old = sc->rho;
+            sc->rho = tot[0];
+            sc->rnorm2 = tot[1];
+            sc->its += 1;
+            if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+                sc->breakdown = 2;
+            } else if (tot[1] <= sc->tol2) {
+                sc->converged = 1;
+            } else if (tot[1] > 1e12 * sc->bnorm2) {
+                sc->breakdown = 1;  // diverged
+            } else if (!(fabs(tot[0]) > 1e-9 * sqrt(sc->rh2 * tot[1])) || sc->omega == 0.0 ||
+                       tot[1] > 1e6 * sc->rmin2) {
+                // (rhat, r) lost its size relative to |rhat||r|, omega vanished, or the
+                // residual grew 1000x above its best value: restart from the current r
+                sc->restart_at = sc->its;
+                sc->rho = tot[1];
+                sc->rh2 = tot[1];
+            }
+            sc->rmin2 = fmin(sc->rmin2, tot[1]);
+        }
+    }
+}
+
+// CG: x += alpha p; r -= alpha q; z = Dinv r; rho_new = (r, z); |r|^2; beta = rho_new / rho
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_xr(int64_t N, T *__restrict__ x, T *__restrict__ r,
+                                                    T *__restrict__ z, const T *__restrict__ p,
+                                                    const T *__restrict__ q, const T *__restrict__ dinv,
+                                                    double *partials, KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const T al = T(sc->alpha);
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
+        x[i] += al * p[i];
+        T ri = r[i] - al * q[i];
+        r[i] = ri;
+        T zi = dinv[i] * ri;
+        z[i] = zi;
+        d0 += double(ri) * double(zi);
+        d1 += double(ri) * double(ri);
+    }
+    double v[2] = {d0, d1};
+    if (block_partials<2>(v, partials, sc->counters)) {
+        double tot[2];
+        finish_partials<2>(partials, tot);
+        if (threadIdx.x == 0) {
+            sc->rho_old = sc->rho;
+            sc->rho = tot[0];
+            sc->beta = tot[0] / sc->rho_old;
+            sc->rnorm2 = tot[1];
+            sc->its += 1;
+            if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->breakdown = 2;
+            else if (tot[1] <= sc->tol2) sc->converged = 1;
+        }
+    }
+}
+
+// CG: p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_p(int64_t N, const T *__restrict__ z, T *__restrict__ p,
+                                                   const KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const T bt = T(sc->beta);
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
+        p[i] = z[i] + bt * p[i];
+}
+
+// Krylov start with x0 = 0: r = rh = b, p = v = 0 (BiCGSTAB) or r = b, z = Dinv b,
+// p = z (CG); reduces |b|^2 and the first rho.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kry_init(int64_t N, int cg, const T *__restrict__ b,
+                                                       T *__restrict__ x, T *__restrict__ r, T *__restrict__ rh,
+                                                       T *__restrict__ p, T *__restrict__ v,
+                                                       const T *__restrict__ dinv, double *partials,
+                                                       KrylovScalars *sc, double rtol) {
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
+        T bi = b[i];
+        x[i] = T(0);
+        r[i] = bi;
+        if (cg) {
+            T zi = dinv[i] * bi;
+            rh[i] = zi;  // z
+            p[i] = zi;
+            d0 += double(bi) * double(zi);
+        } else {
+            rh[i] = bi;
+            p[i] = T(0);
+            v[i] = T(0);
+            d0 += double(bi) * double(bi);
+        }
+        d1 += double(bi) * double(bi);
+    }
+    double vv[2] = {d0, d1};
+    if (block_partials<2>(vv, partials, sc->counters)) {
+        double tot[2];
+        finish_partials<2>(partials, tot);
+        if (threadIdx.x == 0) {
+            sc->rho = tot[0];
+            sc->rho_old = 1.0;
+            sc->alpha = 1.0;
+            sc->omega = 1.0;
+            sc->beta = 0.0;
+            sc->bnorm2 = tot[1];
+            sc->rnorm2 = tot[1];
+            sc->tol2 = rtol * rtol * tot[1];
+            sc->its = 0;
+            sc->rh2 = tot[1];
+            sc->rmin2 = tot[1];
+            sc->restart_at = -1;
+            sc->breakdown = isfinite(tot[1]) ? 0 : 2;
+            sc->converged = (tot[1] == 0.0) ? 1 : 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ vector helpers
+__global__ __launch_bounds__(kThreads) void k_dot_self(int64_t N, const double *__restrict__ r, double *partials,
+                                                       double *out, unsigned *counter) {
+    double d = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
+        d += r[i] * r[i];
+    double v[1] = {d};
+    if (block_partials<1>(v, partials, counter)) {
+        double tot[1];
+        finish_partials<1>(partials, tot);
+        if (threadIdx.x == 0) *out = tot[0];
+    }
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(kThreads) void k_scale_cast(int64_t n, const TI *__restrict__ in, TO *__restrict__ out,
+                                                         double alpha) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) out[i] = TO(alpha * double(in[i]));
+}
+
+template <typename TI>
+__global__ __launch_bounds__(kThreads) void k_axpy_f64(int64_t n, const TI *__restrict__ x, double *__restrict__ y) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) y[i] += double(x[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_set_dirichlet(int64_t n, const uint8_t *__restrict__ mask,
+                                                            double *__restrict__ u, const double *__restrict__ u0,
+                                                            const double *__restrict__ g, double lam) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n && mask[i]) u[i] = u0[i] + lam * (g[i] - u0[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_dirichlet_increment(int64_t n, const uint8_t *__restrict__ mask,
+                                                                  const double *__restrict__ u,
+                                                                  const double *__restrict__ u0,
+                                                                  const double *__restrict__ g, double lam,
+                                                                  double *__restrict__ delta) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) delta[i] = mask[i] ? (u0[i] + lam * (g[i] - u0[i]) - u[i]) : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_neg_sum(int64_t n, const double *__restrict__ a,
+                                                      const double *__restrict__ b, double *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) out[i] = -(a[i] + b[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_mask_copy(int64_t n, const uint8_t *__restrict__ mask,
+                                                        const double *__restrict__ in, double *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) out[i] = (mask && mask[i]) ? 0.0 : in[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_sub(int64_t n, const double *__restrict__ a,
+                                                  const double *__restrict__ b, double *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
+// ------------------------------------------------------------------ pattern export
+template <int ND>
+__global__ __launch_bounds__(kThreads) void k_export_cols(int64_t nnzb, const int64_t *__restrict__ node_ptr,
+                                                          const int32_t *__restrict__ node_nb,
+                                                          const int32_t *__restrict__ blk_row,
+                                                          const int32_t *__restrict__ mirror,
+                                                          const int64_t *__restrict__ row_ptr,
+                                                          int32_t *__restrict__ col_idx, int32_t *__restrict__ tperm) {
+    int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (t >= nnzb * ND * ND) return;
+    int64_t kb = t / (ND * ND);
+    int r = int(t - kb * ND * ND);
+    int i = r / ND, k = r % ND;
+    int64_t n = blk_row[kb], m = node_nb[kb];
+    int64_t pos = row_ptr[ND * n + i] + ND * (kb - node_ptr[n]) + k;
+    if (col_idx) col_idx[pos] = int32_t(ND * m + k);
+    if (tperm) tperm[pos] = int32_t(row_ptr[ND * m + k] + ND * (mirror[kb] - node_ptr[m]) + i);
+}
+
+template <int ND>
+__global__ __launch_bounds__(kThreads) void k_export_slots(int64_t Ne, const int32_t *__restrict__ conn,
+                                                           const int32_t *__restrict__ bslot,
+                                                           const int64_t *__restrict__ node_ptr,
+                                                           const int64_t *__restrict__ row_ptr,
+                                                           int32_t *__restrict__ slot) {
+    constexpr int Nd = 8 * ND;
+    int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (t >= Ne * Nd * Nd) return;
+    int64_t e = t / (Nd * Nd);
+    int r = int(t - e * Nd * Nd);
+    int p = r / Nd, q = r % Nd;
+    int a = p / ND, i = p % ND, b = q / ND, k = q % ND;
+    int64_t n = conn[8 * e + a];
+    int64_t kb = bslot[e * 64 + a * 8 + b];
+    slot[t] = int32_t(row_ptr[ND * n + i] + ND * (kb - node_ptr[n]) + k);
+}
+
+template <int ND>
+__global__ __launch_bounds__(kThreads) void k_export_diag(int64_t N, const int32_t *__restrict__ bdiag,
+                                                          const int64_t *__restrict__ node_ptr,
+                                                          const int64_t *__restrict__ row_ptr,
+                                                          int64_t *__restrict__ diag) {
+    int64_t d = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (d >= N) return;
+    int64_t n = d / ND;
+    int i = int(d - n * ND);
+    diag[d] = row_ptr[d] + ND * (bdiag[n] - node_ptr[n]) + i;
+}
+
+}  // namespace
+
+int krylov_grid(const fem_handle *h) {
+    // Largest persistent grid: 8 resident blocks of 4 waves per CU (8 waves per SIMD).
+    return std::min(8 * h->num_cus, kMaxReduceBlocks);
+}
+
+// Persistent grid of a kernel: the blocks that can be resident at once (runtime
+// occupancy of this kernel variant), a multiple of the 8 XCDs.
+template <typename K>
+static int resident_grid(const fem_handle *h, K kernel) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int G = std::min(per_cu, 8) * h->num_cus;
+    return std::max(8, (G / 8) * 8);
+}
+
+size_t krylov_partials_bytes(const fem_handle *h) { return size_t(krylov_grid(h)) * 2 * sizeof(double); }
+
+template <int ND, int G, typename T>
+static void spmv_launch(const fem_handle *h, const T *values, int transpose, const T *x, T *y, T alpha, T beta,
+                        hipStream_t s) {
+    const Graph &g = h->g;
+    dim3 grid(grid_for(g.Nn, kThreads / G));
+    if (transpose)
+        hipLaunchKernelGGL((k_spmv<ND, G, true, T>), grid, dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, g.mirror,
+                           values, x, y, alpha, beta);
+    else
+        hipLaunchKernelGGL((k_spmv_nodes<ND, 4, 0, T>), dim3(resident_grid(h, k_spmv_nodes<ND, 4, 0, T>)),
+                           dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values, x, y, nullptr, alpha, beta,
+                           nullptr, nullptr, 0);
+}
+
+#define FEM_DISPATCH_GROUP(G_RT, ND_RT, CALL)                                                      \
+    do {                                                                                           \
+        if ((ND_RT) == 1) {                                                                        \
+            constexpr int ND = 1;                                                                  \
+            switch (G_RT) {                                                                        \
+            case 4: { constexpr int G = 4; CALL; break; }                                          \
+            case 8: { constexpr int G = 8; CALL; break; }                                          \
+            case 16: { constexpr int G = 16; CALL; break; }                                        \
+            default: { constexpr int G = 32; CALL; break; }                                        \
+            }                                                                                      \
+        } else {                                                                                   \
+            constexpr int ND = 3;                                                                  \
+            switch (G_RT) {                                                                        \
+            case 4: { constexpr int G = 4; CALL; break; }                                          \
+            case 8: { constexpr int G = 8; CALL; break; }                                          \
+            case 16: { constexpr int G = 16; CALL; break; }                                        \
+            default: { constexpr int G = 32; CALL; break; }                                        \
+            }                                                                                      \
+        }                                                                                          \
+    } while (0)
+
+template <typename T>
+void launch_spmv(const fem_handle *h, const T *values, int transpose, const T *x, T *y, T alpha, T beta,
+                 hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Nn == 0) return;
+    FEM_DISPATCH_GROUP(h->spmv_group, g.nd, (spmv_launch<ND, G, T>(h, values, transpose, x, y, alpha, beta, s)));
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void kry_bicg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s) {
+    hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 0, b, k.x, k.r, k.rh, k.p,
+                       k.v, k.dinv, k.partials, k.sc, rtol);
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s) {
+    // CG keeps z in the slot of rh
+    hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 1, b, k.x, k.r, k.rh, k.p,
+                       k.v, k.dinv, k.partials, k.sc, rtol);
+    FEM_HIP(hipGetLastError());
+}
+
+template <int ND, int P, int MODE, typename T>
+static void kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
+                            const T *values, hipStream_t s) {
+    const Graph &g = h->g;
+    hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T>), dim3(resident_grid(h, k_spmv_nodes<ND, P, MODE, T>)),
+                       dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values, x, y, w0, T(1), T(0), k.partials,
+                       k.sc, cg);
+}
+
+template <typename T, int MODE>
+static void kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
+                     const T *values, hipStream_t s) {
+    // nodes in flight per 32-lane group (tuning knob reused from the group setting)
+    const int P = h->spmv_group <= 4 ? 1 : (h->spmv_group == 8 ? 2 : (h->spmv_group == 16 ? 4 : 8));
+    if (h->g.nd == 1) {
+        if (P == 1) kry_spmv_launch<1, 1, MODE, T>(h, x, y, w0, k, cg, values, s);
+        else if (P == 2) kry_spmv_launch<1, 2, MODE, T>(h, x, y, w0, k, cg, values, s);
+        else if (P == 4) kry_spmv_launch<1, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
+        else kry_spmv_launch<1, 8, MODE, T>(h, x, y, w0, k, cg, values, s);
+    } else {
+        if (P == 1) kry_spmv_launch<3, 1, MODE, T>(h, x, y, w0, k, cg, values, s);
+        else if (P == 2) kry_spmv_launch<3, 2, MODE, T>(h, x, y, w0, k, cg, values, s);
+        else if (P == 4) kry_spmv_launch<3, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
+        else kry_spmv_launch<3, 8, MODE, T>(h, x, y, w0, k, cg, values, s);
+    }
+}
+
+template <typename T>
+void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev) {
+    const int64_t N = h->g.N;
+    dim3 grid(krylov_grid(h)), blk(kThreads);
+    const T *A = k.A;
+    hipLaunchKernelGGL((k_bicg_p<T>), grid, blk, 0, s, N, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
+    if (ev) FEM_HIP(hipEventRecord(ev[0], s));
+    kry_spmv<T, 1>(h, k.ph, k.v, k.rh, k, 0, A, s);
+    if (ev) FEM_HIP(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL((k_bicg_s<T>), grid, blk, 0, s, N, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
+    if (ev) FEM_HIP(hipEventRecord(ev[2], s));
+    kry_spmv<T, 2>(h, k.sh, k.t, k.s, k, 0, A, s);
+    if (ev) FEM_HIP(hipEventRecord(ev[3], s));
+    hipLaunchKernelGGL((k_bicg_xr<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.ph, k.s, k.sh, k.t, k.partials, k.sc);
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev) {
+    const int64_t N = h->g.N;
+    dim3 grid(krylov_grid(h)), blk(kThreads);
+    const T *A = k.A;
+    // slots: z = rh, q = v
+    if (ev) FEM_HIP(hipEventRecord(ev[0], s));
+    kry_spmv<T, 1>(h, k.p, k.v, k.p, k, 1, A, s);
+    if (ev) FEM_HIP(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL((k_cg_xr<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.p, k.v, k.dinv, k.partials, k.sc);
+    hipLaunchKernelGGL((k_cg_p<T>), grid, blk, 0, s, N, k.rh, k.p, k.sc);
+    FEM_HIP(hipGetLastError());
+}
+
+template void kry_bicg_init<float>(const fem_handle *, const KrylovVecs<float> &, const float *, double, hipStream_t);
+template void kry_bicg_init<double>(const fem_handle *, const KrylovVecs<double> &, const double *, double,
+                                    hipStream_t);
+template void kry_cg_init<float>(const fem_handle *, const KrylovVecs<float> &, const float *, double, hipStream_t);
+template void kry_cg_init<double>(const fem_handle *, const KrylovVecs<double> &, const double *, double, hipStream_t);
+template void kry_bicg_iter<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t, hipEvent_t *);
+template void kry_bicg_iter<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t, hipEvent_t *);
+template void kry_cg_iter<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t, hipEvent_t *);
+template void kry_cg_iter<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t, hipEvent_t *);
+template void launch_spmv<float>(const fem_handle *, const float *, int, const float *, float *, float, float,
+                                 hipStream_t);
+template void launch_spmv<double>(const fem_handle *, const double *, int, const double *, double *, double, double,
+                                  hipStream_t);
+
+void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, unsigned *counter,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_self, dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, r, partials, out, counter);
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename TO, typename TI>
+void launch_scale_cast(const TI *in, TO *out, double alpha, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_scale_cast<TO, TI>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, in, out, alpha);
+    FEM_HIP(hipGetLastError());
+}
+template void launch_scale_cast<float, double>(const double *, float *, double, int64_t, hipStream_t);
+template void launch_scale_cast<double, double>(const double *, double *, double, int64_t, hipStream_t);
+template void launch_scale_cast<double, float>(const float *, double *, double, int64_t, hipStream_t);
+
+template <typename TI>
+void launch_axpy_to_f64(const TI *x, double *y, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_axpy_f64<TI>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, x, y);
+    FEM_HIP(hipGetLastError());
+}
+template void launch_axpy_to_f64<float>(const float *, double *, int64_t, hipStream_t);
+template void launch_axpy_to_f64<double>(const double *, double *, int64_t, hipStream_t);
+
+void launch_set_dirichlet(const fem_handle *h, double *u, const double *u0, const double *g, double lam,
+                          hipStream_t s) {
+    if (h->g.N == 0) return;
+    hipLaunchKernelGGL(k_set_dirichlet, dim3(grid_for(h->g.N, kThreads)), dim3(kThreads), 0, s, h->g.N, h->m.mask, u,
+                       u0, g, lam);
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_dirichlet_increment(const fem_handle *h, const double *u, const double *u0, const double *g, double lam,
+                                double *delta, hipStream_t s) {
+    if (h->g.N == 0) return;
+    hipLaunchKernelGGL(k_dirichlet_increment, dim3(grid_for(h->g.N, kThreads)), dim3(kThreads), 0, s, h->g.N,
+                       h->m.mask, u, u0, g, lam, delta);
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_neg_sum(const double *a, const double *b, double *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_neg_sum, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, a, b, out);
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_mask_copy(const fem_handle *h, const double *in, double *out, hipStream_t s) {
+    if (h->g.N == 0) return;
+    hipLaunchKernelGGL(k_mask_copy, dim3(grid_for(h->g.N, kThreads)), dim3(kThreads), 0, s, h->g.N, h->m.mask, in,
+                       out);
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_sub(const double *a, const double *b, double *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_sub, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, a, b, out);
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_export(const fem_handle *h, int64_t *row_ptr, int32_t *col_idx, int32_t *slot, int64_t *diag,
+                   int32_t *tperm, hipStream_t s) {
+    const Graph &g = h->g;
+    if (row_ptr) FEM_HIP(hipMemcpyAsync(row_ptr, g.row_ptr, (g.N + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    const int nd = g.nd;
+    if ((col_idx || tperm) && g.nnz > 0) {
+        dim3 grid(grid_for(g.nnz, kThreads));
+        if (nd == 1)
+            hipLaunchKernelGGL(k_export_cols<1>, grid, dim3(kThreads), 0, s, g.nnzb, g.node_ptr, g.node_nb, g.blk_row,
+                               g.mirror, g.row_ptr, col_idx, tperm);
+        else
+            hipLaunchKernelGGL(k_export_cols<3>, grid, dim3(kThreads), 0, s, g.nnzb, g.node_ptr, g.node_nb, g.blk_row,
+                               g.mirror, g.row_ptr, col_idx, tperm);
+    }
+    if (slot && g.Ne > 0) {
+        int64_t tot = g.Ne * 64 * nd * nd;
+        dim3 grid(grid_for(tot, kThreads));
+        if (nd == 1)
+            hipLaunchKernelGGL(k_export_slots<1>, grid, dim3(kThreads), 0, s, g.Ne, h->m.conn, g.bslot, g.node_ptr,
+                               g.row_ptr, slot);
+        else
+            hipLaunchKernelGGL(k_export_slots<3>, grid, dim3(kThreads), 0, s, g.Ne, h->m.conn, g.bslot, g.node_ptr,
+                               g.row_ptr, slot);
+    }
+    if (diag && g.N > 0) {
+        dim3 grid(grid_for(g.N, kThreads));
+        if (nd == 1)
+            hipLaunchKernelGGL(k_export_diag<1>, grid, dim3(kThreads), 0, s, g.N, g.bdiag, g.node_ptr, g.row_ptr, diag);
+        else
+            hipLaunchKernelGGL(k_export_diag<3>, grid, dim3(kThreads), 0, s, g.N, g.bdiag, g.node_ptr, g.row_ptr, diag);
+    }
+    FEM_HIP(hipGetLastError());
+}
+
+}  // namespace fem

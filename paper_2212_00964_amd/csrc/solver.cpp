@@ -1,0 +1,369 @@
+// Host drivers of the hot path: Newton's method with incremental loading, the
+// Jacobi-preconditioned Krylov solves inside it, and the adjoint gradient.  Every
+// arithmetic step runs in device kernels; the host only sequences launches and
+// reads a few scalars back (the Newton residual norm once per iteration, the
+// Krylov convergence flags every `check_every` iterations).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "solver.h"
+
+namespace fem {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace.
+struct Carver {
+    char *base;
+    size_t used = 0, cap;
+    bool dry;
+    Carver(void *b, size_t c, bool d) : base(static_cast<char *>(b)), cap(c), dry(d) {}
+    template <typename T>
+    T *take(int64_t n) {
+        size_t off = used;
+        used = align_up(used + size_t(std::max<int64_t>(n, 1)) * sizeof(T));
+        if (dry) return nullptr;
+        if (used > cap) throw Error(FEM_ENOMEM, "workspace smaller than fem_workspace_bytes()");
+        return reinterpret_cast<T *>(base + off);
+    }
+};
+
+}  // namespace
+
+void check_status(fem_handle *h, hipStream_t s) {
+    FEM_HIP(hipMemcpyAsync(h->host_status, h->status, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    int st = *h->host_status;
+    if (st & ST_MESH) throw Error(FEM_EMESH, "non-positive Jacobian determinant at a Gauss point (invalid element)");
+    if (st & ST_INVERTED) throw Error(FEM_EINVERTED, "det(F) <= 0 at a Gauss point (inverted material)");
+    if (st & ST_NAN) throw Error(FEM_ENAN, "NaN or Inf in a residual, tangent or diagonal");
+}
+
+void reset_status(fem_handle *h, hipStream_t s) { FEM_HIP(hipMemsetAsync(h->status, 0, sizeof(int), s)); }
+
+template <typename T>
+static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_ke) {
+    const Graph &g = h->g;
+    const int64_t N = g.N;
+    w.r64 = c.take<double>(N);
+    w.u0 = c.take<double>(N);
+    w.res64 = c.take<double>(N);
+    w.lam64 = c.take<double>(N);
+    w.rscr = c.take<double>(g.Ne * 8 * g.nd);
+    w.ke = need_ke ? static_cast<void *>(c.take<T>(g.Ne * 64 * g.nd * g.nd)) : nullptr;
+    w.values = c.take<T>(g.nnz);
+    w.b = c.take<T>(N);
+    T *v[10];
+    for (auto &p : v) p = c.take<T>(N);
+    w.x = v[0];
+    w.r = v[1];
+    w.rh = v[2];
+    w.p = v[3];
+    w.v = v[4];
+    w.s = v[5];
+    w.t = v[6];
+    w.ph = v[7];
+    w.sh = v[8];
+    w.dinv = v[9];
+    w.partials = c.take<double>(2 * int64_t(krylov_grid(h)));
+    w.norm_partials = c.take<double>(krylov_grid(h));
+    w.sc = c.take<KrylovScalars>(1);
+    w.norm_out = c.take<double>(1);
+    w.norm_counter = c.take<unsigned>(kCounterSlots);
+}
+
+size_t solve_workspace_bytes(const fem_handle *h, const fem_solve_opts *o) {
+    Carver c(nullptr, 0, true);
+    SolveWork w;
+    if (o == nullptr) {
+        c.take<double>(h->g.Ne * 64 * h->g.nd * h->g.nd);  // FP64 element blocks
+        c.take<double>(h->g.Ne * 8 * h->g.nd);            // element vectors
+        return c.used;
+    }
+    if (o->precision == FEM_PREC_MIXED) carve_solve<float>(c, h, w, true);
+    else carve_solve<double>(c, h, w, true);
+    return c.used;
+}
+
+void carve_assemble(const fem_handle *h, void *ws, size_t bytes, void **ke, double **rscr, int dtype) {
+    Carver c(ws, bytes, false);
+    if (dtype == FEM_F32) *ke = c.take<float>(h->g.Ne * 64 * h->g.nd * h->g.nd);
+    else *ke = c.take<double>(h->g.Ne * 64 * h->g.nd * h->g.nd);
+    *rscr = c.take<double>(h->g.Ne * 8 * h->g.nd);
+}
+
+double norm2(fem_handle *h, const double *r, SolveWork &w, hipStream_t s) {
+    launch_norm2_free(h, r, w.norm_partials, w.norm_out, w.norm_counter, s);
+    FEM_HIP(hipMemcpyAsync(h->host_scalar, w.norm_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    return std::sqrt(*h->host_scalar);
+}
+
+// Jacobi-preconditioned Krylov solve K x = b (x0 = 0) to ||b - K x|| <= rtol ||b||
+// (recursive residual).  Returns the iteration count; throws on breakdown before
+// any progress.
+template <typename T>
+int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &o, double rtol,
+                 fem_solve_stats *st, hipStream_t s) {
+    KrylovVecs<T> k{A,
+                    static_cast<T *>(w.x),
+                    static_cast<T *>(w.r),
+                    static_cast<T *>(w.rh),
+                    static_cast<T *>(w.p),
+                    static_cast<T *>(w.v),
+                    static_cast<T *>(w.s),
+                    static_cast<T *>(w.t),
+                    static_cast<T *>(w.ph),
+                    static_cast<T *>(w.sh),
+                    static_cast<T *>(w.dinv),
+                    w.partials,
+                    w.sc};
+    const bool cg = o.krylov == FEM_KRYLOV_CG;
+    const T *b = static_cast<const T *>(w.b);
+    FEM_HIP(hipMemsetAsync(w.sc->counters, 0, sizeof(w.sc->counters), s));
+    if (cg) kry_cg_init<T>(h, k, b, rtol, s);
+    else kry_bicg_init<T>(h, k, b, rtol, s);
+    const int every = std::max(1, o.check_every);
+    const int spmv_per_it = cg ? 1 : 2;
+    std::vector<hipEvent_t> &ev = h->events;
+    const bool prof = o.profile_spmv != 0;
+    if (prof && ev.size() < size_t(4 * every)) {
+        size_t old = ev.size();
+        ev.resize(4 * every);
+        for (size_t i = old; i < ev.size(); ++i) FEM_HIP(hipEventCreate(&ev[i]));
+    }
+    int its_done = 0;
+    KrylovScalars hs{};
+    for (int it = 0;; it += every) {
+        for (int j = 0; j < every; ++j) {
+            hipEvent_t *e = prof ? &ev[4 * j] : nullptr;
+            if (cg) kry_cg_iter<T>(h, k, s, e);
+            else kry_bicg_iter<T>(h, k, s, e);
+        }
+        FEM_HIP(hipMemcpyAsync(h->host_kry, w.sc, kScalarsHostBytes, hipMemcpyDeviceToHost, s));
+        FEM_HIP(hipStreamSynchronize(s));
+        std::memcpy(&hs, h->host_kry, kScalarsHostBytes);
+        if (prof && st) {
+            int ran = hs.its - its_done;
+            for (int j = 0; j < ran && j < every; ++j)
+                for (int q = 0; q < spmv_per_it; ++q) {
+                    float ms = 0.f;
+                    FEM_HIP(hipEventElapsedTime(&ms, ev[4 * j + 2 * q], ev[4 * j + 2 * q + 1]));
+                    st->spmv_ms_total += ms;
+                    st->spmv_calls += 1;
+                }
+        }
+        its_done = hs.its;
+        if (hs.converged) break;
+        if (hs.breakdown) {
+            if (hs.breakdown == 2) throw Error(FEM_ENAN, "NaN/Inf in a Krylov inner product");
+            if (hs.its == 0) throw Error(FEM_EBREAKDOWN, "Krylov breakdown before the first update");
+            break;  // keep the last iterate; the outer loop measures its true residual
+        }
+        if (it + every >= o.krylov_max_it) break;
+    }
+    const double relres = hs.bnorm2 > 0.0 ? std::sqrt(hs.rnorm2 / hs.bnorm2) : 0.0;
+    if (st) {
+        st->krylov_its_total += hs.its;
+        if (!hs.converged) st->krylov_unconverged++;
+        if (st->n_hist < FEM_MAX_HIST) st->krylov_relres[st->n_hist] = relres;
+    }
+    // An unconverged solve is still a usable inexact correction as long as it reduced
+    // the residual; one that grew it is rejected.
+    if (!hs.converged && !(relres < 1.0))
+        throw Error(hs.breakdown ? FEM_EBREAKDOWN : FEM_EMAXITER,
+                    "Krylov solve stopped after " + std::to_string(hs.its) + " iterations with ||r||/||b|| = " +
+                        std::to_string(relres));
+    return hs.its;
+}
+
+template int krylov_solve<float>(fem_handle *, SolveWork &, const float *, const fem_solve_opts &, double,
+                                 fem_solve_stats *, hipStream_t);
+template int krylov_solve<double>(fem_handle *, SolveWork &, const double *, const fem_solve_opts &, double,
+                                  fem_solve_stats *, hipStream_t);
+
+using clk = std::chrono::steady_clock;
+static double ms_since(clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+template <typename T>
+static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const double *theta, hipStream_t s) {
+    launch_tangent<T>(h, u, theta, static_cast<T *>(w.ke), static_cast<T *>(w.values), s);
+    launch_extract_dinv<T>(h, static_cast<const T *>(w.values), static_cast<T *>(w.dinv), s);
+}
+
+// One correction: assemble K(u), solve K du = b (b already in w.b), u += du.
+template <typename T>
+static int correction(fem_handle *h, SolveWork &w, double *u, const double *theta, const fem_solve_opts &o,
+                      fem_solve_stats *st, double rn, hipStream_t s) {
+    const int64_t N = h->g.N;
+    auto t0 = clk::now();
+    assemble_into<T>(h, w, u, theta, s);
+    check_status(h, s);
+    if (st) st->ms_assemble += ms_since(t0);
+    t0 = clk::now();
+    int kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, o.krylov_rtol, st, s);
+    launch_axpy_to_f64<T>(static_cast<const T *>(w.x), u, N, s);
+    FEM_HIP(hipStreamSynchronize(s));
+    if (st) {
+        st->ms_krylov += ms_since(t0);
+        if (st->n_hist < FEM_MAX_HIST) {
+            st->krylov_its[st->n_hist] = kits;
+            st->residual_hist[st->n_hist] = rn;
+            st->n_hist++;
+        }
+        st->newton_its++;
+    }
+    return kits;
+}
+
+// Newton's method with incremental loading.  The first iteration of a load step
+// carries the Dirichlet increment D through the tangent at the previous state
+// (du_D = D, K_ff du_f = -r_f - K_fD D); the following iterations solve
+// K(u) du = -r(u) with the Dirichlet rows and columns eliminated.
+template <typename T>
+static void newton_impl(fem_handle *h, double *u, const double *theta, const double *gD, const fem_solve_opts &o,
+                        fem_solve_stats *st, void *ws, size_t wsb, hipStream_t s) {
+    Carver c(ws, wsb, false);
+    SolveWork w;
+    carve_solve<T>(c, h, w, true);
+    const int64_t N = h->g.N;
+    auto t_all = clk::now();
+    reset_status(h, s);
+    FEM_HIP(hipMemsetAsync(w.norm_counter, 0, kCounterSlots * sizeof(unsigned), s));
+    FEM_HIP(hipMemcpyAsync(w.u0, u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int nsteps = std::max(1, o.n_load_steps);
+    for (int k = 1; k <= nsteps; ++k) {
+        const double lam = double(k) / nsteps;
+        auto t0 = clk::now();
+        launch_dirichlet_increment(h, u, w.u0, gD, lam, w.res64, s);
+        launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
+        launch_lift(h, u, theta, w.res64, w.rscr, w.lam64, s);
+        launch_neg_sum(w.r64, w.lam64, w.r64, N, s);  // predictor right-hand side
+        const double bn = norm2(h, w.r64, w, s);
+        check_status(h, s);
+        if (st) st->ms_residual += ms_since(t0);
+        if (!std::isfinite(bn)) throw Error(FEM_ENAN, "non-finite Newton right-hand side");
+        const double ref = std::max(bn, lam * h->m.fext_norm);
+        const double tol = std::max(o.newton_rtol * ref, o.newton_atol);
+        if (st) {
+            st->initial_residual = bn;
+            st->load_steps = k;
+        }
+        const int fixed = o.newton_fixed_its;
+        int it = 0;
+        if (bn > tol || fixed > 0) {
+            if (o.newton_max_it < 1) throw Error(FEM_EMAXITER, "newton_max_it = 0");
+            launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), 1.0, N, s);
+            correction<T>(h, w, u, theta, o, st, bn, s);
+            ++it;
+        }
+        launch_set_dirichlet(h, u, w.u0, gD, lam, s);
+        t0 = clk::now();
+        launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
+        double rn = norm2(h, w.r64, w, s);
+        check_status(h, s);
+        if (st) st->ms_residual += ms_since(t0);
+        while (fixed > 0 ? it < fixed : !(rn <= tol)) {
+            if (!std::isfinite(rn)) throw Error(FEM_ENAN, "non-finite Newton residual");
+            if (rn > 1e8 * std::max(ref, 1e-300)) throw Error(FEM_EDIVERGED, "Newton residual diverged");
+            if (fixed == 0 && it >= o.newton_max_it)
+                throw Error(FEM_EMAXITER, "Newton did not converge in load step " + std::to_string(k) +
+                                              " (|r| = " + std::to_string(rn) + ", tol = " + std::to_string(tol) + ")");
+            launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), -1.0, N, s);
+            correction<T>(h, w, u, theta, o, st, rn, s);
+            t0 = clk::now();
+            launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
+            rn = norm2(h, w.r64, w, s);
+            check_status(h, s);
+            if (st) st->ms_residual += ms_since(t0);
+            ++it;
+        }
+        if (st) st->final_residual = rn;
+    }
+    if (st) st->ms_total += ms_since(t_all);
+}
+
+void newton_solve(fem_handle *h, double *u, const double *theta, const double *gD, const fem_solve_opts &o,
+                  fem_solve_stats *st, void *ws, size_t wsb, hipStream_t s) {
+    if (o.precision == FEM_PREC_MIXED) newton_impl<float>(h, u, theta, gD, o, st, ws, wsb, s);
+    else newton_impl<double>(h, u, theta, gD, o, st, ws, wsb, s);
+}
+
+template <typename T>
+static void adjoint_impl(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *g,
+                         double *lam_out, const fem_solve_opts &o, fem_solve_stats *st, void *ws, size_t wsb,
+                         hipStream_t s) {
+    Carver c(ws, wsb, false);
+    SolveWork w;
+    carve_solve<T>(c, h, w, true);
+    const int64_t N = h->g.N;
+    auto t_all = clk::now();
+    reset_status(h, s);
+    FEM_HIP(hipMemsetAsync(w.norm_counter, 0, kCounterSlots * sizeof(unsigned), s));
+    auto t0 = clk::now();
+    // All laws here have major-symmetric tangents and the Dirichlet elimination is
+    // symmetric, so (dC/du)^T is the assembled K itself.
+    assemble_into<T>(h, w, u, theta, s);
+    launch_mask_copy(h, dJdu, w.res64, s);  // b = dJ/du with Dirichlet entries 0
+    double bn = norm2(h, w.res64, w, s);
+    check_status(h, s);
+    if (st) st->ms_assemble += ms_since(t0);
+    FEM_HIP(hipMemsetAsync(w.lam64, 0, N * sizeof(double), s));
+    FEM_HIP(hipMemcpyAsync(w.r64, w.res64, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // r64 = b
+    double rn = bn;
+    const double tol = std::max(o.adjoint_rtol * bn, 0.0);
+    int sweeps = 0;
+    while (rn > tol) {
+        if (!std::isfinite(rn)) throw Error(FEM_ENAN, "non-finite adjoint residual");
+        if (sweeps >= o.adjoint_max_refine) throw Error(FEM_EMAXITER, "adjoint refinement did not converge");
+        t0 = clk::now();
+        launch_scale_cast<T, double>(w.res64, static_cast<T *>(w.b), 1.0, N, s);
+        int kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, o.krylov_rtol, st, s);
+        launch_axpy_to_f64<T>(static_cast<const T *>(w.x), w.lam64, N, s);
+        if (st) {
+            st->ms_krylov += ms_since(t0);
+            if (st->n_hist < FEM_MAX_HIST) {
+                st->krylov_its[st->n_hist] = kits;
+                st->residual_hist[st->n_hist] = rn;
+                st->n_hist++;
+            }
+        }
+        // FP64 refinement residual with the matrix-free tangent: res = b - K(u) lambda
+        t0 = clk::now();
+        launch_apply_tangent(h, u, theta, w.lam64, w.rscr, w.u0, s);
+        launch_sub(w.r64, w.u0, w.res64, N, s);
+        launch_mask_copy(h, w.res64, w.res64, s);
+        rn = norm2(h, w.res64, w, s);
+        check_status(h, s);
+        if (st) st->ms_residual += ms_since(t0);
+        ++sweeps;
+    }
+    t0 = clk::now();
+    launch_vjp(h, u, theta, w.lam64, g, s);
+    if (lam_out) FEM_HIP(hipMemcpyAsync(lam_out, w.lam64, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    check_status(h, s);
+    if (st) {
+        st->ms_vjp += ms_since(t0);
+        st->final_residual = rn;
+        st->initial_residual = bn;
+        st->newton_its += sweeps;
+        st->ms_total += ms_since(t_all);
+    }
+}
+
+void adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *g,
+                 double *lam_out, const fem_solve_opts &o, fem_solve_stats *st, void *ws, size_t wsb,
+                 hipStream_t s) {
+    if (o.precision == FEM_PREC_MIXED) adjoint_impl<float>(h, u, theta, dJdu, g, lam_out, o, st, ws, wsb, s);
+    else adjoint_impl<double>(h, u, theta, dJdu, g, lam_out, o, st, ws, wsb, s);
+}
+
+}  // namespace fem

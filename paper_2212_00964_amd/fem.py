@@ -1,0 +1,322 @@
+"""Thin Python binding of libfem (ctypes).
+
+Only argument marshalling happens here: device memory comes from torch tensors,
+the stream is torch's current stream, and every step of the computation runs in
+the library's HIP kernels.  If libfem.so is not built the binding raises; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import inputs
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libfem.so"
+
+FEM_OK = 0
+ERRORS = {-1: "FEM_EINVAL", -2: "FEM_ERANGE", -3: "FEM_EHIP", -4: "FEM_EMESH", -5: "FEM_EINVERTED",
+          -6: "FEM_ENAN", -7: "FEM_EBREAKDOWN", -8: "FEM_EMAXITER", -9: "FEM_EDIVERGED", -10: "FEM_ENOMEM"}
+F32, F64 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+CG, BICGSTAB = 0, 1
+MAX_HIST = 64
+
+
+class FemLibraryMissing(RuntimeError):
+    pass
+
+
+class FemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64), ("ndpn", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("pmap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nu", ctypes.c_double), ("bulk_ratio", ctypes.c_double), ("simp_p", ctypes.c_double),
+                ("simp_emin", ctypes.c_double), ("simp_e0", ctypes.c_double), ("coords", ctypes.c_void_p),
+                ("conn", ctypes.c_void_p), ("dirichlet_mask", ctypes.c_void_p), ("f_nodal", ctypes.c_void_p),
+                ("source_nodal", ctypes.c_void_p), ("n_traction_faces", ctypes.c_int64),
+                ("traction_faces", ctypes.c_void_p), ("traction", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("krylov", ctypes.c_int32), ("n_load_steps", ctypes.c_int32),
+                ("newton_max_it", ctypes.c_int32), ("newton_rtol", ctypes.c_double),
+                ("newton_atol", ctypes.c_double), ("krylov_rtol", ctypes.c_double),
+                ("krylov_max_it", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("adjoint_rtol", ctypes.c_double), ("adjoint_max_refine", ctypes.c_int32),
+                ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int32), ("load_steps", ctypes.c_int32), ("krylov_its_total", ctypes.c_int32),
+                ("n_hist", ctypes.c_int32), ("initial_residual", ctypes.c_double),
+                ("final_residual", ctypes.c_double), ("ms_residual", ctypes.c_double),
+                ("ms_assemble", ctypes.c_double), ("ms_krylov", ctypes.c_double), ("ms_vjp", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("spmv_calls", ctypes.c_int32), ("krylov_unconverged", ctypes.c_int32),
+                ("spmv_ms_total", ctypes.c_double), ("krylov_its", ctypes.c_int32 * MAX_HIST),
+                ("residual_hist", ctypes.c_double * MAX_HIST), ("krylov_relres", ctypes.c_double * MAX_HIST)]
+
+    def as_dict(self) -> dict:
+        arrays = ("krylov_its", "residual_hist", "krylov_relres")
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in arrays}
+        for k in arrays:
+            d[k] = list(getattr(self, k)[:self.n_hist])
+        return d
+
+
+# Names, in the order the header declares them (checked by the CPU test-suite).
+EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
+           "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv", "fem_apply_tangent",
+           "fem_newton_solve", "fem_adjoint_vjp"]
+
+_lib = None
+
+
+def library_path() -> pathlib.Path:
+    return _LIB_PATH
+
+
+def lib():
+    """Loads libfem.so; raises FemLibraryMissing if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise FemLibraryMissing(f"{_LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(str(_LIB_PATH))
+    vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "fem_last_error": (ctypes.c_char_p, []),
+        "fem_default_opts": (ctypes.c_int, [P(SolveOpts)]),
+        "fem_build_pattern": (ctypes.c_int, [P(MeshDesc), P(vp), P(i64), P(i64)]),
+        "fem_destroy": (None, [vp]),
+        "fem_pattern_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fem_load_vector": (ctypes.c_int, [vp, vp, vp]),
+        "fem_workspace_bytes": (ctypes.c_int, [vp, P(SolveOpts), P(sz)]),
+        "fem_assemble": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, sz, vp]),
+        "fem_spmv": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, dbl, dbl, vp]),
+        "fem_apply_tangent": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "fem_newton_solve": (ctypes.c_int, [vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
+        "fem_adjoint_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, stats=None):
+    if rc != FEM_OK:
+        e = FemError(rc, lib().fem_last_error().decode())
+        e.stats = stats
+        raise e
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    _check(lib().fem_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _host(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+class Problem:
+    """A mesh + material + loads bound to a libfem handle on the current GPU."""
+
+    def __init__(self, prob: inputs.Problem, device: str = "cuda"):
+        L = lib()
+        self.spec = prob
+        self.device = torch.device(device)
+        self._keep = dict(coords=_host(prob.coords, np.float64), conn=_host(prob.conn, np.int32),
+                          mask=_host(prob.dirichlet_mask, np.uint8), f=_host(prob.f_nodal, np.float64),
+                          src=_host(prob.source_nodal, np.float64),
+                          faces=_host(prob.traction_faces, np.int32), trac=_host(prob.traction, np.float64))
+        k = self._keep
+
+        def p(a):
+            return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        d = MeshDesc(prob.n_nodes, prob.n_elems, prob.ndpn, prob.model, prob.pmap, 0, prob.nu, prob.bulk_ratio,
+                     prob.simp_p, prob.simp_emin, prob.simp_e0, p(k["coords"]), p(k["conn"]), p(k["mask"]),
+                     p(k["f"]), p(k["src"]), 0 if k["faces"] is None else k["faces"].shape[0], p(k["faces"]),
+                     p(k["trac"]))
+        h = ctypes.c_void_p()
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            _check(L.fem_build_pattern(ctypes.byref(d), ctypes.byref(h), ctypes.byref(n), ctypes.byref(nnz)))
+        self.handle = h
+        self.n_dofs = n.value
+        self.nnz = nnz.value
+        self.n_elems = prob.n_elems
+        self._ws = None
+        self.mask = torch.as_tensor(prob.dirichlet_mask.astype(bool), device=self.device)
+        self.dirichlet_values = torch.as_tensor(prob.dirichlet_values, dtype=torch.float64, device=self.device)
+        self.theta = torch.as_tensor(prob.theta, dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().fem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ helpers
+    def workspace_bytes(self, opts: Optional[SolveOpts] = None) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().fem_workspace_bytes(self.handle, None if opts is None else ctypes.byref(opts), ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, opts: Optional[SolveOpts] = None) -> torch.Tensor:
+        need = self.workspace_bytes(opts)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _f64(self, t, n=None):
+        if t is None:
+            return None
+        t = torch.as_tensor(t, dtype=torch.float64, device=self.device).contiguous()
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} entries, got {t.numel()}")
+        return t
+
+    # ------------------------------------------------------------------ entry points
+    def export_pattern(self, slot_map: bool = True, transpose: bool = True) -> dict:
+        N, nnz = self.n_dofs, self.nnz
+        nd = self.spec.ndpn
+        Nd = 8 * nd
+        out = dict(row_ptr=torch.empty(N + 1, dtype=torch.int64, device=self.device),
+                   col_idx=torch.empty(nnz, dtype=torch.int32, device=self.device),
+                   diag_slot=torch.empty(N, dtype=torch.int64, device=self.device))
+        out["slot_map"] = (torch.empty(self.n_elems * Nd * Nd, dtype=torch.int32, device=self.device)
+                           if slot_map else None)
+        out["transpose_perm"] = torch.empty(nnz, dtype=torch.int32, device=self.device) if transpose else None
+        _check(lib().fem_pattern_export(self.handle, _ptr(out["row_ptr"]), _ptr(out["col_idx"]),
+                                        _ptr(out["slot_map"]), _ptr(out["diag_slot"]),
+                                        _ptr(out["transpose_perm"]), _stream()))
+        return out
+
+    def load_vector(self) -> torch.Tensor:
+        f = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        _check(lib().fem_load_vector(self.handle, _ptr(f), _stream()))
+        return f
+
+    def assemble(self, u, theta=None, residual: bool = True, values_dtype: Optional[torch.dtype] = torch.float64):
+        u = self._f64(u, self.n_dofs)
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        r = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device) if residual else None
+        vals = None
+        dt = F64
+        if values_dtype is not None:
+            dt = F32 if values_dtype == torch.float32 else F64
+            vals = torch.empty(self.nnz, dtype=values_dtype, device=self.device)
+        ws = self.workspace(None)
+        _check(lib().fem_assemble(self.handle, _ptr(u), _ptr(theta), _ptr(r), _ptr(vals), dt, _ptr(ws),
+                                  ws.numel(), _stream()))
+        return r, vals
+
+    def spmv(self, values: torch.Tensor, x: torch.Tensor, transpose: bool = False, alpha: float = 1.0,
+             beta: float = 0.0, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        dt = F32 if values.dtype == torch.float32 else F64
+        if values.numel() != self.nnz or x.numel() != self.n_dofs or x.dtype != values.dtype:
+            raise ValueError("spmv operand shapes/dtypes do not match the pattern")
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().fem_spmv(self.handle, _ptr(values), dt, int(transpose), _ptr(x), _ptr(y), alpha, beta,
+                              _stream()))
+        return y
+
+    def apply_tangent(self, u, v, theta=None) -> torch.Tensor:
+        u = self._f64(u, self.n_dofs)
+        v = self._f64(v, self.n_dofs)
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        y = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        ws = self.workspace(None)
+        _check(lib().fem_apply_tangent(self.handle, _ptr(u), _ptr(theta), _ptr(v), _ptr(y), _ptr(ws), ws.numel(),
+                                       _stream()))
+        return y
+
+    def opts(self, **kw) -> SolveOpts:
+        kw.setdefault("krylov", self.spec.krylov)
+        kw.setdefault("n_load_steps", self.spec.n_load_steps)
+        return default_opts(**kw)
+
+    def newton_solve(self, theta=None, u0=None, dirichlet_values=None, opts: Optional[SolveOpts] = None, **kw):
+        opts = self.opts(**kw) if opts is None else opts
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        u = (torch.zeros(self.n_dofs, dtype=torch.float64, device=self.device) if u0 is None
+             else self._f64(u0, self.n_dofs).clone())
+        g = self.dirichlet_values if dirichlet_values is None else self._f64(dirichlet_values, self.n_dofs)
+        st = SolveStats()
+        ws = self.workspace(opts)
+        _check(lib().fem_newton_solve(self.handle, _ptr(u), _ptr(theta), _ptr(g), ctypes.byref(opts),
+                                      ctypes.byref(st), _ptr(ws), ws.numel(), _stream()), st)
+        return u, st
+
+    def adjoint_vjp(self, u, dJdu, theta=None, opts: Optional[SolveOpts] = None, want_lambda: bool = True, **kw):
+        opts = self.opts(**kw) if opts is None else opts
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        u = self._f64(u, self.n_dofs)
+        dJdu = self._f64(dJdu, self.n_dofs)
+        g = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
+        lam = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device) if want_lambda else None
+        st = SolveStats()
+        ws = self.workspace(opts)
+        _check(lib().fem_adjoint_vjp(self.handle, _ptr(u), _ptr(theta), _ptr(dJdu), _ptr(g), _ptr(lam),
+                                     ctypes.byref(opts), ctypes.byref(st), _ptr(ws), ws.numel(), _stream()), st)
+        return g, lam, st
+
+
+class FemSolve(torch.autograd.Function):
+    """u = U(theta): forward = Newton solve, backward = adjoint VJP (Sec. 3, Eq. (adjoint_chain_simp)).
+
+    ``backward(grad_u)`` returns -lambda^T dC/dtheta with (dC/du)^T lambda = grad_u; the
+    explicit dJ/dtheta term of a loss is added by torch autograd on the loss itself."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, problem: Problem, opts: Optional[SolveOpts] = None):
+        u, st = problem.newton_solve(theta=theta.detach(), opts=opts)
+        ctx.problem = problem
+        ctx.opts = opts
+        ctx.stats = st
+        ctx.save_for_backward(theta.detach(), u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        theta, u = ctx.saved_tensors
+        g, _, _ = ctx.problem.adjoint_vjp(u, grad_u.detach().to(torch.float64).contiguous(), theta=theta,
+                                          opts=ctx.opts, want_lambda=False)
+        return g.to(theta.dtype), None, None
