@@ -4,7 +4,8 @@
 Workload: compressible neo-Hookean block, 100x100x100 HEX8 on the unit cube
 (1,000,000 elements, 3,090,903 dofs), per-element shear modulus lognormal
 (mu = ln 10, sigma = 0.3, seed 0), bulk modulus 10x shear, pulled to stretch 1.2
-in 5 load steps, Jacobi-preconditioned BiCGSTAB inside Newton.
+in 5 load steps, Jacobi-preconditioned Krylov (CG by default: the tangent is SPD;
+the paper's BiCGSTAB with --krylov bicgstab) inside Newton.
 
 One timed step = one Newton iteration of load step 5 (starting from the converged
 state of load step 4: residual, Dirichlet lifting, tangent assembly, Jacobi
@@ -35,14 +36,15 @@ def log(*a):
 
 
 def spmv_bytes(prob, value_bytes):
-    """Algorithmic bytes of one fused Krylov SpMV launch: CSR values, one column index
-    per node block, node row pointers, x gathered once, y written, one dot vector read."""
-    g = prob
-    n_blocks = g.nnz // (g.spec.ndpn ** 2)
-    return (g.nnz * value_bytes + n_blocks * 4 + (g.spec.n_nodes + 1) * 8 + 3 * g.n_dofs * value_bytes)
+    """Algorithmic bytes of one fused Krylov SpMV launch: CSR values, one 32-bit column
+    index per node block, node row pointers, x gathered once, y written, one dot vector
+    read."""
+    nd = prob.spec.ndpn
+    n_blocks = prob.nnz // (nd * nd)
+    return prob.nnz * value_bytes + n_blocks * 4 + (prob.spec.n_nodes + 1) * 8 + 3 * prob.n_dofs * value_bytes
 
 
-def cpu_baseline(gpu_counts, size_z=20):
+def cpu_baseline(gpu_counts, size_z=20, method="cg"):
     """Times the CPU oracle (single-threaded, as written) on a slab of the same workload
     and scales the measured per-unit costs to the full problem and to the iteration
     counts the GPU step performed."""
@@ -69,8 +71,8 @@ def cpu_baseline(gpu_counts, size_z=20):
     it_out, rel = ctypes.c_int(0), ctypes.c_double(0.0)
     b = -r
     t0 = time.perf_counter()
-    orc.lib().orc_bicgstab(pat.n, pat.row_ptr, pat.col_idx, vals, b, x, 1e-30, its, ctypes.byref(it_out),
-                           ctypes.byref(rel))
+    solver = orc.lib().orc_pcg if method == "cg" else orc.lib().orc_bicgstab
+    solver(pat.n, pat.row_ptr, pat.col_idx, vals, b, x, 1e-30, its, ctypes.byref(it_out), ctypes.byref(rel))
     t_it = (time.perf_counter() - t0) / max(it_out.value, 1)
     t0 = time.perf_counter()
     orc.vjp_theta(p, u, x)
@@ -80,7 +82,7 @@ def cpu_baseline(gpu_counts, size_z=20):
     return {"value": newton_ms + adjoint_ms, "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": (f"oracle (plain C, 1 thread) on a {p.shape[0]}x{p.shape[1]}x{p.shape[2]} slab "
                        f"({p.n_elems} elements, {p.n_dofs} dofs) of the same workload: residual {t_res:.2f}s, "
-                       f"tangent assembly {t_asm:.2f}s, BiCGSTAB {1e3 * t_it:.1f} ms/iteration over {it_out.value} "
+                       f"tangent assembly {t_asm:.2f}s, {method} {1e3 * t_it:.1f} ms/iteration over {it_out.value} "
                        f"iterations, VJP {t_vjp:.2f}s; scaled x{scale:g} to 1M elements and to the GPU step's "
                        f"{gpu_counts['newton_krylov_its']} + {gpu_counts['adjoint_krylov_its']} Krylov iterations "
                        f"(pattern build {t_pat:.1f}s not counted)"),
@@ -94,9 +96,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, nargs=3, default=[100, 100, 100])
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--krylov-rtol", type=float, default=1e-4)
+    ap.add_argument("--krylov", choices=["cg", "bicgstab"], default="cg")
+    ap.add_argument("--krylov-rtol", type=float, default=1e-3)
+    ap.add_argument("--adjoint-rtol", type=float, default=1e-6)
     ap.add_argument("--no-compare", action="store_true", help="skip the full FP64-vs-mixed 5-step solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="short run for hardware counters: one bounded Krylov solve (64 iterations) of the "
+                         "workload plus a 256 MiB device copy as the counter calibration; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is built and measured on a single MI355X "
@@ -114,27 +121,41 @@ def main():
     prob = fem.Problem(p, "cuda:0")
     log(f"pattern + upload {time.perf_counter() - t0:.1f}s, nnz={prob.nnz}")
     prec = fem.PREC_MIXED if args.precision == "mixed" else fem.PREC_FP64
+    kry = fem.CG if args.krylov == "cg" else fem.BICGSTAB
     g_final = prob.dirichlet_values
 
+    if args.profile_kernels:
+        o = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_fixed_its=1, krylov_rtol=1e-12,
+                      krylov_max_it=64, check_every=64)
+        prob.newton_solve(dirichlet_values=0.2 * g_final, opts=o)
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)  # 256 MiB read + 256 MiB written: calibrates FETCH_SIZE / WRITE_SIZE
+        torch.cuda.synchronize()
+        log("profile run done")
+        prob.close()
+        return
+
     # converged state of load step 4 (schedule 0.2, 0.4, 0.6, 0.8 of the final stretch)
-    o4 = prob.opts(precision=prec, n_load_steps=4, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol)
+    o4 = prob.opts(precision=prec, krylov=kry, n_load_steps=4, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol)
     t0 = time.perf_counter()
     u4, st4 = prob.newton_solve(dirichlet_values=0.8 * g_final, opts=o4)
     log(f"load steps 1-4: {time.perf_counter() - t0:.2f}s newton_its={st4.newton_its} "
         f"krylov_its={st4.krylov_its_total}")
-    o5 = prob.opts(precision=prec, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol)
+    o5 = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol)
     u5, st5 = prob.newton_solve(u0=u4, opts=o5)
     log(f"load step 5: newton_its={st5.newton_its} krylov_its={list(st5.krylov_its[:st5.n_hist])}")
     dJdu = torch.where(prob.mask, torch.zeros_like(u5), u5)
 
-    step_opts = prob.opts(precision=prec, n_load_steps=1, newton_fixed_its=1, krylov_rtol=args.krylov_rtol,
-                          profile_spmv=1)
-    adj_opts = prob.opts(precision=prec, krylov_rtol=args.krylov_rtol, adjoint_rtol=1e-8, profile_spmv=1)
+    step_opts = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_fixed_its=1,
+                          krylov_rtol=args.krylov_rtol, profile_spmv=1)
+    adj_opts = prob.opts(precision=prec, krylov=kry, krylov_rtol=args.krylov_rtol, adjoint_rtol=args.adjoint_rtol,
+                         profile_spmv=1)
 
     def step():
         u, sn = prob.newton_solve(u0=u4, opts=step_opts)
         g, _, sa = prob.adjoint_vjp(u5, dJdu, opts=adj_opts, want_lambda=False)
-        return sn, sa
+        return sn, sa, g
 
     for _ in range(args.warmup):
         step()
@@ -142,7 +163,7 @@ def main():
     newton_ms, adj_ms, spmv_ms, spmv_calls, kits_n, kits_a = [], [], 0.0, 0, [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        sn, sa = step()
+        sn, sa, g_step = step()
         newton_ms.append(sn.ms_total)
         adj_ms.append(sa.ms_total)
         spmv_ms += sn.spmv_ms_total + sa.spmv_ms_total
@@ -168,40 +189,52 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"neo-Hookean tensile block {nx}x{ny}x{nz} HEX8 ({p.n_elems} elements, "
                                f"{p.n_dofs} dofs, nnz {prob.nnz}), lognormal G (ln 10, 0.3), kappa = 10 G, "
-                               f"load step 5 of 5 to stretch 1.2; Jacobi-BiCGSTAB (rtol {args.krylov_rtol:g})",
+                               f"load step 5 of 5 to stretch 1.2; Jacobi-{args.krylov} (inner rtol "
+                               f"{args.krylov_rtol:g}), adjoint rtol {args.adjoint_rtol:g}",
                    "precision": args.precision, "parallelism": "single GPU"},
         "newton_step_ms": t_newton, "adjoint_grad_ms": t_adj,
         "dofs_per_s": p.n_dofs / ((t_newton + t_adj) * 1e-3),
+        "krylov": args.krylov, "krylov_rtol": args.krylov_rtol, "adjoint_rtol": args.adjoint_rtol,
         "krylov_its": {"newton": int(np.median(kits_n)), "adjoint": int(np.median(kits_a))},
-        "roofline": {"bound": "hbm", "kernel": "k_kry_spmv (fused SpMV + FP64 dot)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_nodes (fused Krylov SpMV + FP64 dot)", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "avg_launch_us": avg_spmv_ms * 1e3, "launches": spmv_calls, "bytes_per_launch": nbytes},
     }
 
     if not args.no_compare:
+        # FP64 reference gradient (tight), then full 5-step solves of each form
+        g_ref, _, _ = prob.adjoint_vjp(u5, dJdu, opts=prob.opts(precision=fem.PREC_FP64, krylov=fem.CG,
+                                                                krylov_rtol=1e-8, adjoint_rtol=1e-11),
+                                       want_lambda=False)
+        out["grad_rel_err_vs_fp64"] = float(torch.linalg.norm(g_step - g_ref) / torch.linalg.norm(g_ref))
+        u_ref, _ = prob.newton_solve(opts=prob.opts(precision=fem.PREC_FP64, krylov=fem.CG, krylov_rtol=1e-8,
+                                                    newton_rtol=1e-11))
         res = {}
-        for name, pr, rt, kr in (("mixed", fem.PREC_MIXED, 1e-9, args.krylov_rtol), ("fp64", fem.PREC_FP64, 1e-10, 1e-6)):
-            o = prob.opts(precision=pr, newton_rtol=rt, krylov_rtol=kr)
+        forms = (("mixed-" + args.krylov, prec if prec == fem.PREC_MIXED else fem.PREC_MIXED, kry, args.krylov_rtol),
+                 ("fp64-cg", fem.PREC_FP64, fem.CG, args.krylov_rtol),
+                 ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB, args.krylov_rtol))
+        for name, pr, kr, eta in forms:
+            o = prob.opts(precision=pr, krylov=kr, newton_rtol=1e-9, krylov_rtol=eta)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             u, st = prob.newton_solve(opts=o)
             torch.cuda.synchronize()
-            res[name] = (u, time.perf_counter() - t0, st)
-            log(f"full 5-step solve {name}: {res[name][1]:.2f}s newton_its={st.newton_its} "
-                f"krylov_its={st.krylov_its_total}")
-        um, ud = res["mixed"][0], res["fp64"][0]
-        out["full_solve"] = {
-            "mixed_s": res["mixed"][1], "fp64_s": res["fp64"][1],
-            "mixed_newton_its": res["mixed"][2].newton_its, "fp64_newton_its": res["fp64"][2].newton_its,
-            "mixed_krylov_its": res["mixed"][2].krylov_its_total, "fp64_krylov_its": res["fp64"][2].krylov_its_total,
-            "mixed_rel_err_vs_fp64": float(torch.linalg.norm(um - ud) / torch.linalg.norm(ud)),
-            "speedup_mixed_over_fp64": res["fp64"][1] / res["mixed"][1]}
+            dt = time.perf_counter() - t0
+            err = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
+            res[name] = {"s": dt, "newton_its": st.newton_its, "krylov_its": st.krylov_its_total,
+                         "rel_err_vs_tight_fp64": err}
+            log(f"full 5-step solve {name}: {dt:.2f}s newton_its={st.newton_its} krylov_its={st.krylov_its_total} "
+                f"err={err:.2e}")
+        mixed_name = forms[0][0]
+        res["speedup_mixed_over_fp64_cg"] = res["fp64-cg"]["s"] / res[mixed_name]["s"]
+        res["speedup_mixed_over_fp64_bicgstab"] = res["fp64-bicgstab"]["s"] / res[mixed_name]["s"]
+        out["full_solve"] = res
 
     prob.close()
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline({"newton_krylov_its": int(np.median(kits_n)),
-                                            "adjoint_krylov_its": int(np.median(kits_a))})
+                                            "adjoint_krylov_its": int(np.median(kits_a))}, method=args.krylov)
         log(f"cpu baseline {time.perf_counter() - t0:.1f}s: {out['cpu_baseline']['value']:.0f} ms")
     print(json.dumps(out), flush=True)
 

@@ -60,6 +60,14 @@ extern "C" {
 enum { FEM_POISSON = 0, FEM_LINEAR_ELASTIC = 1, FEM_NEO_HOOKEAN = 2 };
 enum { FEM_THETA_IDENTITY = 0, FEM_THETA_SIMP = 1 };
 enum { FEM_F32 = 0, FEM_F64 = 1 };
+/* Storage of tangent values.
+ * FEM_LAYOUT_CSR: CSR over all dofs (row_ptr / col_idx of fem_pattern_export).
+ * FEM_LAYOUT_SYM_BLOCK: the matrix is symmetric (all models here, with the symmetric
+ *   Dirichlet elimination), so only the ndpn x ndpn blocks (n, m) with m >= n are
+ *   stored: in CSR order of the node graph (node n ascending, then neighbour m
+ *   ascending), each block row-major; block (m, n) with m > n is read as the
+ *   transpose of block (n, m).  About half the values of the CSR layout. */
+enum { FEM_LAYOUT_CSR = 0, FEM_LAYOUT_SYM_BLOCK = 1 };
 /* FEM_PREC_FP64: tangent, SpMV and Krylov vectors in FP64.
  * FEM_PREC_MIXED: tangent values, SpMV and Krylov vectors in FP32 with FP32
  * accumulation; the Newton/refinement residual, the adjoint refinement residual
@@ -159,6 +167,9 @@ void fem_destroy(fem_handle *h);
 int fem_pattern_export(fem_handle *h, int64_t *row_ptr, int32_t *col_idx, int32_t *slot_map, int64_t *diag_slot,
                        int32_t *transpose_perm, void *stream);
 
+/* Number of stored tangent values in `layout` (nnz for FEM_LAYOUT_CSR). */
+int fem_values_count(fem_handle *h, int32_t layout, int64_t *count);
+
 /* Copies the external load vector F_ext [N] (FP64) into a caller device buffer. */
 int fem_load_vector(fem_handle *h, double *f_ext, void *stream);
 
@@ -168,17 +179,18 @@ int fem_workspace_bytes(fem_handle *h, const fem_solve_opts *opts, size_t *bytes
 
 /* Residual and tangent at u (Sec. 2.2: R_e and K_e = dr_e/dU_e, Alg. 1 assembly):
  *   residual [N] FP64 (may be NULL): r = R_int(u; theta) - F_ext, Dirichlet entries 0;
- *   values [nnz] (may be NULL): K(u) in CSR order, FEM_F32 or FEM_F64, with the
- *   symmetric Dirichlet elimination.  u [N] FP64, theta [n_elems] FP64.
+ *   values [fem_values_count(layout)] (may be NULL): K(u) in `values_layout`,
+ *   FEM_F32 or FEM_F64, with the symmetric Dirichlet elimination.
+ *   u [N] FP64, theta [n_elems] FP64.
  * Blocks until the kernels finish and reports FEM_EMESH / FEM_EINVERTED / FEM_ENAN. */
 int fem_assemble(fem_handle *h, const double *u, const double *theta, double *residual, void *values,
-                 int32_t values_dtype, void *workspace, size_t workspace_bytes, void *stream);
+                 int32_t values_dtype, int32_t values_layout, void *workspace, size_t workspace_bytes, void *stream);
 
-/* y = alpha * op(K) x + beta * y with op(K) = K or K^T (transpose != 0); values, x and
- * y all of `dtype`; accumulation in that dtype.  With beta == 0, y is not read.
- * Asynchronous on `stream`. */
-int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t transpose, const void *x, void *y,
-             double alpha, double beta, void *stream);
+/* y = alpha * op(K) x + beta * y with op(K) = K or K^T (transpose != 0; for
+ * FEM_LAYOUT_SYM_BLOCK both are K); values, x and y all of `dtype`; products and
+ * sums in that dtype.  With beta == 0, y is not read.  Asynchronous on `stream`. */
+int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t layout, int32_t transpose, const void *x,
+             void *y, double alpha, double beta, void *stream);
 
 /* Tangent-vector product y = K(u) v, matrix-free in FP64, with the same Dirichlet
  * elimination as the assembled matrix (y_d = v_d on Dirichlet dofs, Dirichlet

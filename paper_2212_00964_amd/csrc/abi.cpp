@@ -180,11 +180,21 @@ int fem_workspace_bytes(fem_handle *h, const fem_solve_opts *o, size_t *bytes) {
     });
 }
 
+int fem_values_count(fem_handle *h, int32_t layout, int64_t *count) {
+    return guarded([&] {
+        require(h != nullptr && count != nullptr, "handle and count must be non-NULL");
+        require(layout == FEM_LAYOUT_CSR || layout == FEM_LAYOUT_SYM_BLOCK, "layout");
+        *count = layout == FEM_LAYOUT_CSR ? h->g.nnz : h->g.nnzb_up * h->g.nd * h->g.nd;
+    });
+}
+
 int fem_assemble(fem_handle *h, const double *u, const double *theta, double *residual, void *values,
-                 int32_t values_dtype, void *workspace, size_t workspace_bytes, void *stream) {
+                 int32_t values_dtype, int32_t values_layout, void *workspace, size_t workspace_bytes, void *stream) {
     return guarded([&] {
         require(h != nullptr, "handle is NULL");
         require(values_dtype == FEM_F32 || values_dtype == FEM_F64, "values_dtype");
+        require(values_layout == FEM_LAYOUT_CSR || values_layout == FEM_LAYOUT_SYM_BLOCK, "values_layout");
+        const int ly = values_layout == FEM_LAYOUT_SYM_BLOCK ? fem::LAYOUT_SYM : fem::LAYOUT_CSR;
         const bool work = h->g.N > 0 && (residual || values);
         if (!work) return;
         require(u != nullptr && theta != nullptr, "u and theta must be non-NULL");
@@ -197,22 +207,34 @@ int fem_assemble(fem_handle *h, const double *u, const double *theta, double *re
         fem::reset_status(h, s);
         if (residual) fem::launch_residual(h, u, theta, 1.0, rscr, residual, s);
         if (values) {
-            if (values_dtype == FEM_F32) fem::launch_tangent<float>(h, u, theta, static_cast<float *>(ke),
-                                                                     static_cast<float *>(values), s);
-            else fem::launch_tangent<double>(h, u, theta, static_cast<double *>(ke), static_cast<double *>(values), s);
+            if (values_dtype == FEM_F32)
+                fem::launch_tangent<float>(h, u, theta, static_cast<float *>(ke), static_cast<float *>(values), s, ly);
+            else
+                fem::launch_tangent<double>(h, u, theta, static_cast<double *>(ke), static_cast<double *>(values), s,
+                                            ly);
         }
         fem::check_status(h, s);
     });
 }
 
-int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t transpose, const void *x, void *y,
-             double alpha, double beta, void *stream) {
+int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t layout, int32_t transpose, const void *x,
+             void *y, double alpha, double beta, void *stream) {
     return guarded([&] {
         require(h != nullptr, "handle is NULL");
         require(dtype == FEM_F32 || dtype == FEM_F64, "dtype");
+        require(layout == FEM_LAYOUT_CSR || layout == FEM_LAYOUT_SYM_BLOCK, "layout");
         if (h->g.N == 0) return;
         require(values && x && y, "values, x and y must be non-NULL");
         bind_device(h);
+        if (layout == FEM_LAYOUT_SYM_BLOCK) {
+            if (dtype == FEM_F32)
+                fem::launch_spmv_sym<float>(h, static_cast<const float *>(values), static_cast<const float *>(x),
+                                            static_cast<float *>(y), float(alpha), float(beta), as_stream(stream));
+            else
+                fem::launch_spmv_sym<double>(h, static_cast<const double *>(values), static_cast<const double *>(x),
+                                             static_cast<double *>(y), alpha, beta, as_stream(stream));
+            return;
+        }
         if (dtype == FEM_F32)
             fem::launch_spmv<float>(h, static_cast<const float *>(values), transpose, static_cast<const float *>(x),
                                     static_cast<float *>(y), float(alpha), float(beta), as_stream(stream));

@@ -426,17 +426,22 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
     }
 }
 
-// CSR values from element blocks: thread (block kb, row component i) writes the ND
-// entries values[row_ptr[ND*n+i] + ND*j + k], k < ND, of block kb = (n, j-th
-// neighbour m), summing the contributing element blocks in element order, then
-// applies the symmetric Dirichlet elimination.
-template <int ND, typename T>
+// Tangent values from element blocks: thread (block kb, row component i) sums the
+// contributing element blocks of node-graph block kb = (n, j-th neighbour m) in
+// element order, applies the symmetric Dirichlet elimination and writes row i of
+// the block once:
+//   LAYOUT_CSR: values[row_ptr[ND*n+i] + ND*j + k], k < ND;
+//   LAYOUT_SYM: only blocks with m >= n, block-major at values[ND*ND*(up_base[n] +
+//               kb - bdiag[n]) + ND*i + k] (the lower blocks are their transposes).
+template <int ND, int LAYOUT, typename T>
 __global__ __launch_bounds__(256) void k_gather_values(int64_t nnzb, const int64_t *__restrict__ node_ptr,
                                                        const int32_t *__restrict__ node_nb,
                                                        const int32_t *__restrict__ blk_row,
                                                        const int64_t *__restrict__ blk_ptr,
                                                        const int32_t *__restrict__ blk_src,
                                                        const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ bdiag,
+                                                       const int64_t *__restrict__ up_base,
                                                        const uint8_t *__restrict__ mask, const T *__restrict__ ke,
                                                        T *__restrict__ values, int *status) {
     int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -445,7 +450,7 @@ __global__ __launch_bounds__(256) void k_gather_values(int64_t nnzb, const int64
     int i = int(t - kb * ND);
     int64_t n = blk_row[kb];
     int64_t m = node_nb[kb];
-    int64_t j = kb - node_ptr[n];
+    if (LAYOUT == LAYOUT_SYM && m < n) return;
     T acc[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) acc[k] = T(0);
@@ -456,7 +461,8 @@ __global__ __launch_bounds__(256) void k_gather_values(int64_t nnzb, const int64
     }
     int64_t row = ND * n + i;
     bool bad = false;
-    T *dst = values + row_ptr[row] + ND * j;
+    T *dst = (LAYOUT == LAYOUT_SYM) ? values + ND * ND * (up_base[n] + kb - bdiag[n]) + ND * i
+                                    : values + row_ptr[row] + ND * (kb - node_ptr[n]);
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
         int64_t col = ND * m + k;
@@ -468,17 +474,19 @@ __global__ __launch_bounds__(256) void k_gather_values(int64_t nnzb, const int64
     if (bad) atomicOr(status, ST_NAN);
 }
 
-template <int ND, typename T>
+template <int ND, int LAYOUT, typename T>
 __global__ __launch_bounds__(256) void k_extract_dinv(int64_t N, const int64_t *__restrict__ node_ptr,
                                                       const int32_t *__restrict__ bdiag,
                                                       const int64_t *__restrict__ row_ptr,
+                                                      const int64_t *__restrict__ up_base,
                                                       const T *__restrict__ values, T *__restrict__ dinv,
                                                       int *status) {
     int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (d >= N) return;
     int64_t n = d / ND;
     int i = int(d - n * ND);
-    T v = values[row_ptr[d] + ND * (bdiag[n] - node_ptr[n]) + i];
+    T v = (LAYOUT == LAYOUT_SYM) ? values[ND * ND * up_base[n] + (ND + 1) * i]
+                                 : values[row_ptr[d] + ND * (bdiag[n] - node_ptr[n]) + i];
     if (!(v != T(0)) || !isfinite(v)) atomicOr(status, ST_NAN);
     dinv[d] = T(1) / v;
 }
@@ -556,40 +564,49 @@ void launch_vjp(const fem_handle *h, const double *u, const double *theta, const
 }
 
 template <typename T>
-void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke, T *values, hipStream_t s) {
+void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke, T *values, hipStream_t s,
+                    int layout) {
     const Graph &g = h->g;
-    if (g.Ne == 0) {
-        FEM_HIP(hipMemsetAsync(values, 0, g.nnz * sizeof(T), s));
-        return;
-    }
+    if (g.Ne == 0) return;
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_tangent<MODEL, ND, T>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
                            h->m.conn, h->mat, theta, u, ke, h->status);
-        hipLaunchKernelGGL((k_gather_values<ND, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s, g.nnzb,
-                           g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, h->m.mask, ke, values,
-                           h->status);
+        if (layout == LAYOUT_SYM)
+            hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_SYM, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s,
+                               g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, g.bdiag,
+                               g.up_base, h->m.mask, ke, values, h->status);
+        else
+            hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_CSR, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s,
+                               g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, g.bdiag,
+                               g.up_base, h->m.mask, ke, values, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s) {
+void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s, int layout) {
     const Graph &g = h->g;
     if (g.N == 0) return;
-    if (g.nd == 1)
-        hipLaunchKernelGGL((k_extract_dinv<1, T>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.node_ptr, g.bdiag,
-                           g.row_ptr, values, dinv, h->status);
-    else
-        hipLaunchKernelGGL((k_extract_dinv<3, T>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.node_ptr, g.bdiag,
-                           g.row_ptr, values, dinv, h->status);
+#define FEM_DINV(ND, LY)                                                                                         \
+    hipLaunchKernelGGL((k_extract_dinv<ND, LY, T>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.node_ptr,  \
+                       g.bdiag, g.row_ptr, g.up_base, values, dinv, h->status)
+    if (g.nd == 1) {
+        if (layout == LAYOUT_SYM) FEM_DINV(1, LAYOUT_SYM);
+        else FEM_DINV(1, LAYOUT_CSR);
+    } else {
+        if (layout == LAYOUT_SYM) FEM_DINV(3, LAYOUT_SYM);
+        else FEM_DINV(3, LAYOUT_CSR);
+    }
+#undef FEM_DINV
     FEM_HIP(hipGetLastError());
 }
 
-template void launch_tangent<float>(const fem_handle *, const double *, const double *, float *, float *, hipStream_t);
+template void launch_tangent<float>(const fem_handle *, const double *, const double *, float *, float *, hipStream_t,
+                                    int);
 template void launch_tangent<double>(const fem_handle *, const double *, const double *, double *, double *,
-                                     hipStream_t);
-template void launch_extract_dinv<float>(const fem_handle *, const float *, float *, hipStream_t);
-template void launch_extract_dinv<double>(const fem_handle *, const double *, double *, hipStream_t);
+                                     hipStream_t, int);
+template void launch_extract_dinv<float>(const fem_handle *, const float *, float *, hipStream_t, int);
+template void launch_extract_dinv<double>(const fem_handle *, const double *, double *, hipStream_t, int);
 
 }  // namespace fem

@@ -30,18 +30,14 @@ struct Error : std::runtime_error {
 // Bits of the device status word raised by kernels.
 enum : int { ST_MESH = 1, ST_INVERTED = 2, ST_NAN = 4, ST_BREAKDOWN = 8 };
 
+// Storage of tangent values: full CSR, or only the blocks (n, m) with m >= n.
+enum Layout { LAYOUT_CSR = 0, LAYOUT_SYM = 1 };
+
 // Material description passed by value to kernels.
 struct Material {
     int model, pmap;
     double nu, bulk_ratio, simp_p, simp_emin, simp_e0;
 };
-
-// Completion counters of the grid-wide reductions: a two-level tree with kFanIn
-// blocks per first-level counter and one counter per 128-byte line.
-constexpr int kFanIn = 32;
-constexpr int kCounterStride = 32;
-constexpr int kMaxReduceBlocks = 4096;
-constexpr int kCounterSlots = (kMaxReduceBlocks / kFanIn + 1) * kCounterStride;
 
 // Device-side Krylov scalars (FP64), one instance per solve in the workspace.
 struct KrylovScalars {
@@ -51,10 +47,8 @@ struct KrylovScalars {
     double rmin2;    // smallest |r|^2 reached so far
     int its, converged, breakdown;
     int restart_at;  // BiCGSTAB restarts (rhat = p = r) at the iteration with this index
-    alignas(128) unsigned int counters[kCounterSlots];  // reduction completion tree (self-resetting)
 };
-// Bytes of KrylovScalars read back by the host (everything before the counters).
-constexpr size_t kScalarsHostBytes = offsetof(KrylovScalars, counters);
+constexpr size_t kScalarsHostBytes = sizeof(KrylovScalars);
 
 // Sparsity structure on the device.  A "block" is the ndpn x ndpn coupling of a
 // node pair (n, m); blocks are numbered in CSR order of the node graph.
@@ -72,6 +66,11 @@ struct Graph {
     int32_t *ne_list = nullptr;   // [8*Ne] e*8 + a, element ascending
     int32_t *bslot = nullptr;     // [Ne*64] block of local pair (a, b) of element e
     int64_t *row_ptr = nullptr;   // [N+1] scalar CSR row starts
+    // Symmetric block layout: only blocks (n, m) with m >= n are stored, block-major
+    // (nd x nd, row-major), in CSR order of the node graph.
+    int64_t nnzb_up = 0;
+    int64_t *up_base = nullptr;   // [Nn+1] first stored block of node n
+    int32_t *lo_val = nullptr;    // [nnzb] for a block (n, m) with m < n: stored block (m, n)
 };
 
 // Problem mesh on the device.
@@ -117,19 +116,21 @@ void launch_apply_tangent(const fem_handle *h, const double *u, const double *th
 // ke_scratch: [Ne*64*nd*nd] of the value type; values [nnz].
 template <typename T>
 void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke_scratch, T *values,
-                    hipStream_t s);
+                    hipStream_t s, int layout = LAYOUT_CSR);
 // y = (K(u) v) on free dofs with v used on every dof (Dirichlet lifting), 0 on Dirichlet dofs.
 void launch_lift(const fem_handle *h, const double *u, const double *theta, const double *v, double *scratch,
                  double *y, hipStream_t s);
 void launch_vjp(const fem_handle *h, const double *u, const double *theta, const double *lam, double *g,
                 hipStream_t s);
 template <typename T>
-void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s);
+void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s, int layout = LAYOUT_CSR);
 
 // ------------------------------------------------------------------ sparse / vector kernels
 template <typename T>
 void launch_spmv(const fem_handle *h, const T *values, int transpose, const T *x, T *y, T alpha, T beta,
                  hipStream_t s);
+template <typename T>
+void launch_spmv_sym(const fem_handle *h, const T *values, const T *x, T *y, T alpha, T beta, hipStream_t s);
 void launch_export(const fem_handle *h, int64_t *row_ptr, int32_t *col_idx, int32_t *slot, int64_t *diag,
                    int32_t *tperm, hipStream_t s);
 
@@ -139,7 +140,8 @@ size_t krylov_partials_bytes(const fem_handle *h);
 
 template <typename T>
 struct KrylovVecs {
-    const T *A;  // CSR values of the operator
+    const T *A;  // values of the operator
+    int layout;  // LAYOUT_CSR or LAYOUT_SYM
     T *x, *r, *rh, *p, *v, *s, *t, *ph, *sh, *dinv;
     double *partials;
     KrylovScalars *sc;
@@ -155,8 +157,7 @@ template <typename T>
 void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
 
 // Vector helpers.
-void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, unsigned *counter,
-                       hipStream_t s);
+void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, hipStream_t s);
 template <typename TO, typename TI>
 void launch_scale_cast(const TI *in, TO *out, double alpha, int64_t n, hipStream_t s);
 template <typename TI>

@@ -97,17 +97,14 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int64_t Nn, const int64_t *__
 }
 
 // ------------------------------------------------------------------ deterministic reductions
-// Per-thread values v[0..NV) are reduced over the block; thread 0 stores the block
-// totals to partials[c * gridDim.x + blockIdx.x].  Returns true in the (single) block
-// that finishes last; that block then sees every partial.  Completion is counted in
-// a two-level tree (kFanIn blocks per first-level counter, each counter on its own
-// 128-byte line) so that thousands of blocks never queue on one atomic address.
-__device__ __forceinline__ int counter_groups(unsigned G) { return int((G + kFanIn - 1) / kFanIn); }
-
+// Grid-wide FP64 sums are done in two kernels: every block of the producing kernel
+// stores its block total to partials[c * G + blockIdx.x] (plain stores, no fences or
+// atomics: on a multi-XCD device a device-scope fence per block would write back the
+// XCD's L2 every time), and a one-block finalize kernel launched next on the same
+// stream adds the G partials in block order.  The result is bit-reproducible.
 template <int NV>
-__device__ bool block_partials(const double v[NV], double *partials, unsigned int *counters) {
-    __shared__ double red[kThreads / 64][NV > 0 ? NV : 1];
-    __shared__ bool last;
+__device__ void block_store_partials(const double v[NV], double *partials) {
+    __shared__ double red[kThreads / 64][NV];
     double w[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -128,43 +125,18 @@ __device__ bool block_partials(const double v[NV], double *partials, unsigned in
             for (int k = 0; k < kThreads / 64; ++k) t += red[k][c];
             partials[c * gridDim.x + blockIdx.x] = t;
         }
-        const unsigned G = gridDim.x;
-        const int ng = counter_groups(G);
-        const int grp = int(blockIdx.x / kFanIn);
-        const unsigned members = (unsigned(grp) == unsigned(ng - 1)) ? G - unsigned(grp) * kFanIn : unsigned(kFanIn);
-        bool top = false;
-        __threadfence();
-        unsigned prev = atomicAdd(&counters[grp * kCounterStride], 1u);
-        if (prev == members - 1) {
-            counters[grp * kCounterStride] = 0u;  // every member has arrived: reset for the next kernel
-            __threadfence();
-            unsigned p2 = atomicAdd(&counters[ng * kCounterStride], 1u);
-            top = (p2 == unsigned(ng - 1));
-            if (top) counters[ng * kCounterStride] = 0u;
-        }
-        last = top;
     }
-    __syncthreads();
-    return last;
 }
 
-// Load that bypasses the per-CU vector L1 (other blocks wrote the value through L2).
-__device__ __forceinline__ double load_l2(const double *p) {
-    unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double(static_cast<long long>(v));
-}
-
-// Called by all threads of the last block: totals of every partial, in block order.
+// In a one-block finalize kernel: totals of the G partials of each of NV sums.
 template <int NV>
-__device__ void finish_partials(const double *partials, double tot[NV]) {
+__device__ void sum_partials(const double *partials, int G, double tot[NV]) {
     __shared__ double red[kThreads / 64][NV];
-    __threadfence();
     double v[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
         double t = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += kThreads) t += load_l2(&partials[c * gridDim.x + b]);
+        for (int b = threadIdx.x; b < G; b += kThreads) t += partials[c * G + b];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
         v[c] = t;
@@ -304,26 +276,146 @@ __global__ __launch_bounds__(kThreads) void k_spmv_nodes(int64_t Nn, const int64
     }
     }
     if constexpr (MODE != 0) {
-    double vv[2] = {d0, d1};
-    if (block_partials<MODE>(vv, partials, sc->counters)) {
-        double tot[MODE];
-        finish_partials<MODE>(partials, tot);
-        if (threadIdx.x == 0) {
-            if (MODE == 1) {
-                bool bad = !(tot[0] != 0.0) || !isfinite(tot[0]) || (cg && !(tot[0] > 0.0));
-                if (bad) sc->breakdown = 1;
-                else sc->alpha = sc->rho / tot[0];
-            } else {
-                double tt = tot[1];
-                if (!(tt > 0.0) || !isfinite(tt)) {
-                    sc->omega = 0.0;
-                } else {
-                    sc->omega = tot[0] / tt;
+        double vv[2] = {d0, d1};
+        block_store_partials<MODE>(vv, partials);
+    }
+}
+
+// SpMV on the symmetric block layout (blocks (n, m) with m >= n stored, block-major).
+// Node n's row needs its upper blocks, which are contiguous from up_base[n], and its
+// lower blocks (n, m), m < n, which are the transposes of the stored blocks (m, n)
+// (index lo_val).  Those were streamed moments earlier by the block range holding
+// node m, so they come from L2 or the Infinity Cache; HBM traffic is the stored half
+// of the matrix.  Same persistent scheme as k_spmv_nodes (LDS-staged row data, P
+// nodes in flight per 32-lane group, branch-free loads on clamped addresses).
+template <int ND, int P, int MODE, typename T>
+__global__ __launch_bounds__(kThreads) void k_spmv_sym(int64_t Nn, const int64_t *__restrict__ node_ptr,
+                                                       const int64_t *__restrict__ up_base,
+                                                       const int32_t *__restrict__ node_nb,
+                                                       const int32_t *__restrict__ lo_val,
+                                                       const T *__restrict__ values, const T *__restrict__ x,
+                                                       T *__restrict__ y, const T *__restrict__ w0, T alpha, T beta,
+                                                       double *partials, KrylovScalars *sc, int cg) {
+    constexpr int G = kSpmvGroup;
+    constexpr int GPB = kThreads / G;
+    constexpr int CH = kMaxChunk / 2;
+    constexpr int BS = ND * ND;
+    __shared__ int64_t sptr[CH + 1];
+    __shared__ int64_t sup[CH + 1];
+    if (MODE != 0 && stopped(sc)) return;
+    int64_t r0, r1;
+    block_range(Nn, r0, r1);
+    const int lane = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t n0 = r0; n0 < r1; n0 += CH) {
+        const int cnt = int(r1 - n0 < CH ? r1 - n0 : CH);
+        __syncthreads();
+        for (int i = threadIdx.x; i <= cnt; i += kThreads) {
+            sptr[i] = node_ptr[n0 + i];
+            sup[i] = up_base[n0 + i];
+        }
+        __syncthreads();
+        for (int base = grp; base < cnt; base += P * GPB) {
+            int64_t b0[P], ub[P];
+            int deg[P], dpos[P];
+            int32_t m[P];
+            T v[P][BS];
+            T xm[P][ND];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int ln = base + p * GPB;
+                const bool ok = ln < cnt;
+                b0[p] = ok ? sptr[ln] : 0;
+                deg[p] = ok ? int(sptr[ln + 1] - sptr[ln]) : 0;
+                ub[p] = ok ? sup[ln] : 0;
+                dpos[p] = ok ? deg[p] - int(sup[ln + 1] - sup[ln]) : 0;
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const bool act = lane < deg[p];
+                const bool lower = lane < dpos[p];
+                m[p] = __builtin_nontemporal_load(node_nb + b0[p] + (act ? lane : 0));
+                const int32_t lv = __builtin_nontemporal_load(lo_val + b0[p] + (lower ? lane : 0));
+                const int64_t ku = lower ? int64_t(lv) : (act ? ub[p] + (lane - dpos[p]) : ub[p]);
+                const T *vb = values + BS * ku;
+#pragma unroll
+                for (int q = 0; q < BS; ++q) v[p][q] = vb[q];
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int k = 0; k < ND; ++k) xm[p][k] = x[int64_t(ND) * m[p] + k];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const bool act = lane < deg[p];
+                const bool lower = lane < dpos[p];
+                T acc[ND];
+#pragma unroll
+                for (int i = 0; i < ND; ++i) {
+                    T a = T(0);
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) a += (lower ? v[p][k * ND + i] : v[p][i * ND + k]) * xm[p][k];
+                    acc[i] = act ? a : T(0);
+                }
+                for (int l = lane + G; l < deg[p]; l += G) {  // high-degree nodes
+                    const int64_t mm = node_nb[b0[p] + l];
+                    const bool lw = l < dpos[p];
+                    const int64_t kk = lw ? int64_t(lo_val[b0[p] + l]) : ub[p] + (l - dpos[p]);
+                    const T *vb = values + BS * kk;
+#pragma unroll
+                    for (int i = 0; i < ND; ++i)
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) acc[i] += (lw ? vb[k * ND + i] : vb[i * ND + k]) * x[ND * mm + k];
+                }
+#pragma unroll
+                for (int i = 0; i < ND; ++i) acc[i] = group_sum<G>(acc[i]);
+                const int ln = base + p * GPB;
+                if (ln < cnt && lane < ND) {
+                    T sv = acc[0];
+#pragma unroll
+                    for (int i = 1; i < ND; ++i)
+                        if (lane == i) sv = acc[i];
+                    const int64_t d = int64_t(ND) * (n0 + ln) + lane;
+                    if (MODE == 0) {
+                        T out = alpha * sv;
+                        if (beta != T(0)) out += beta * y[d];
+                        y[d] = out;
+                    } else {
+                        y[d] = sv;
+                        d0 += double(w0[d]) * double(sv);
+                        if (MODE == 2) d1 += double(sv) * double(sv);
+                    }
                 }
             }
         }
     }
+    if constexpr (MODE != 0) {
+        double vv[2] = {d0, d1};
+        block_store_partials<MODE>(vv, partials);
     }
+}
+
+// alpha = rho / (w0, y)
+__global__ __launch_bounds__(kThreads) void k_fin_alpha(int G, const double *__restrict__ partials,
+                                                        KrylovScalars *sc, int cg) {
+    if (stopped(sc)) return;
+    double tot[1];
+    sum_partials<1>(partials, G, tot);
+    if (threadIdx.x == 0) {
+        bool bad = !(tot[0] != 0.0) || !isfinite(tot[0]) || (cg && !(tot[0] > 0.0));
+        if (bad) sc->breakdown = 1;
+        else sc->alpha = sc->rho / tot[0];
+    }
+}
+
+// omega = (t, s) / (t, t)
+__global__ __launch_bounds__(kThreads) void k_fin_omega(int G, const double *__restrict__ partials,
+                                                        KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    double tot[2];
+    sum_partials<2>(partials, G, tot);
+    if (threadIdx.x == 0) sc->omega = (tot[1] > 0.0 && isfinite(tot[1])) ? tot[0] / tot[1] : 0.0;
 }
 
 // BiCGSTAB: beta = (rho/rho_old)(alpha/omega); p = r + beta (p - omega v); ph = Dinv p.
@@ -377,30 +469,35 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t N, T *__restrict__
         d1 += double(ri) * double(ri);
     }
     double v[2] = {d0, d1};
-    if (block_partials<2>(v, partials, sc->counters)) {
-        double tot[2];
-        finish_partials<2>(partials, tot);
-        if (threadIdx.x == 0) {
-            sc->rho_old = sc->rho;
-            sc->rho = tot[0];
-            sc->rnorm2 = tot[1];
-            sc->its += 1;
-            if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-                sc->breakdown = 2;
-            } else if (tot[1] <= sc->tol2) {
-                sc->converged = 1;
-            } else if (tot[1] > 1e12 * sc->bnorm2) {
-                sc->breakdown = 1;  // diverged
-            } else if (!(fabs(tot[0]) > 1e-9 * sqrt(sc->rh2 * tot[1])) || sc->omega == 0.0 ||
-                       tot[1] > 1e6 * sc->rmin2) {
-                // (rhat, r) lost its size relative to |rhat||r|, omega vanished, or the
-                // residual grew 1000x above its best value: restart from the current r
-                sc->restart_at = sc->its;
-                sc->rho = tot[1];
-                sc->rh2 = tot[1];
-            }
-            sc->rmin2 = fmin(sc->rmin2, tot[1]);
+    block_store_partials<2>(v, partials);
+}
+
+// BiCGSTAB: rho_new = (rhat, r), |r|^2; convergence, divergence and restart tests
+__global__ __launch_bounds__(kThreads) void k_fin_bicg_xr(int G, const double *__restrict__ partials,
+                                                          KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    double tot[2];
+    sum_partials<2>(partials, G, tot);
+    if (threadIdx.x == 0) {
+        sc->rho_old = sc->rho;
+        sc->rho = tot[0];
+        sc->rnorm2 = tot[1];
+        sc->its += 1;
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+            sc->breakdown = 2;
+        } else if (tot[1] <= sc->tol2) {
+            sc->converged = 1;
+        } else if (tot[1] > 1e12 * sc->bnorm2) {
+            sc->breakdown = 1;  // diverged
+        } else if (!(fabs(tot[0]) > 1e-9 * sqrt(sc->rh2 * tot[1])) || sc->omega == 0.0 ||
+                   tot[1] > 1e6 * sc->rmin2) {
+            // (rhat, r) lost its size relative to |rhat||r|, omega vanished, or the
+            // residual grew 1000x above its best value: restart from the current r
+            sc->restart_at = sc->its;
+            sc->rho = tot[1];
+            sc->rh2 = tot[1];
         }
+        sc->rmin2 = fmin(sc->rmin2, tot[1]);
     }
 }
 
@@ -423,18 +520,23 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr(int64_t N, T *__restrict__ x
         d1 += double(ri) * double(ri);
     }
     double v[2] = {d0, d1};
-    if (block_partials<2>(v, partials, sc->counters)) {
-        double tot[2];
-        finish_partials<2>(partials, tot);
-        if (threadIdx.x == 0) {
-            sc->rho_old = sc->rho;
-            sc->rho = tot[0];
-            sc->beta = tot[0] / sc->rho_old;
-            sc->rnorm2 = tot[1];
-            sc->its += 1;
-            if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->breakdown = 2;
-            else if (tot[1] <= sc->tol2) sc->converged = 1;
-        }
+    block_store_partials<2>(v, partials);
+}
+
+// CG: rho_new = (r, z), |r|^2, beta = rho_new / rho, convergence test
+__global__ __launch_bounds__(kThreads) void k_fin_cg_xr(int G, const double *__restrict__ partials,
+                                                        KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    double tot[2];
+    sum_partials<2>(partials, G, tot);
+    if (threadIdx.x == 0) {
+        sc->rho_old = sc->rho;
+        sc->rho = tot[0];
+        sc->beta = tot[0] / sc->rho_old;
+        sc->rnorm2 = tot[1];
+        sc->its += 1;
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->breakdown = 2;
+        else if (tot[1] <= sc->tol2) sc->converged = 1;
     }
 }
 
@@ -475,40 +577,44 @@ __global__ __launch_bounds__(kThreads) void k_kry_init(int64_t N, int cg, const 
         d1 += double(bi) * double(bi);
     }
     double vv[2] = {d0, d1};
-    if (block_partials<2>(vv, partials, sc->counters)) {
-        double tot[2];
-        finish_partials<2>(partials, tot);
-        if (threadIdx.x == 0) {
-            sc->rho = tot[0];
-            sc->rho_old = 1.0;
-            sc->alpha = 1.0;
-            sc->omega = 1.0;
-            sc->beta = 0.0;
-            sc->bnorm2 = tot[1];
-            sc->rnorm2 = tot[1];
-            sc->tol2 = rtol * rtol * tot[1];
-            sc->its = 0;
-            sc->rh2 = tot[1];
-            sc->rmin2 = tot[1];
-            sc->restart_at = -1;
-            sc->breakdown = isfinite(tot[1]) ? 0 : 2;
-            sc->converged = (tot[1] == 0.0) ? 1 : 0;
-        }
+    block_store_partials<2>(vv, partials);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fin_init(int G, const double *__restrict__ partials,
+                                                       KrylovScalars *sc, double rtol) {
+    double tot[2];
+    sum_partials<2>(partials, G, tot);
+    if (threadIdx.x == 0) {
+        sc->rho = tot[0];
+        sc->rho_old = 1.0;
+        sc->alpha = 1.0;
+        sc->omega = 1.0;
+        sc->beta = 0.0;
+        sc->bnorm2 = tot[1];
+        sc->rnorm2 = tot[1];
+        sc->tol2 = rtol * rtol * tot[1];
+        sc->its = 0;
+        sc->rh2 = tot[1];
+        sc->rmin2 = tot[1];
+        sc->restart_at = -1;
+        sc->breakdown = isfinite(tot[1]) ? 0 : 2;
+        sc->converged = (tot[1] == 0.0) ? 1 : 0;
     }
 }
 
 // ------------------------------------------------------------------ vector helpers
-__global__ __launch_bounds__(kThreads) void k_dot_self(int64_t N, const double *__restrict__ r, double *partials,
-                                                       double *out, unsigned *counter) {
+__global__ __launch_bounds__(kThreads) void k_dot_self(int64_t N, const double *__restrict__ r, double *partials) {
     double d = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
         d += r[i] * r[i];
     double v[1] = {d};
-    if (block_partials<1>(v, partials, counter)) {
-        double tot[1];
-        finish_partials<1>(partials, tot);
-        if (threadIdx.x == 0) *out = tot[0];
-    }
+    block_store_partials<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fin_dot(int G, const double *__restrict__ partials, double *out) {
+    double tot[1];
+    sum_partials<1>(partials, G, tot);
+    if (threadIdx.x == 0) *out = tot[0];
 }
 
 template <typename TO, typename TI>
@@ -611,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_export_diag(int64_t N, const int32
 
 int krylov_grid(const fem_handle *h) {
     // Largest persistent grid: 8 resident blocks of 4 waves per CU (8 waves per SIMD).
-    return std::min(8 * h->num_cus, kMaxReduceBlocks);
+    return 8 * h->num_cus;
 }
 
 // Persistent grid of a kernel: the blocks that can be resident at once (runtime
@@ -672,9 +778,28 @@ void launch_spmv(const fem_handle *h, const T *values, int transpose, const T *x
 }
 
 template <typename T>
+void launch_spmv_sym(const fem_handle *h, const T *values, const T *x, T *y, T alpha, T beta, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Nn == 0) return;
+#define FEM_SYM0(ND)                                                                                            \
+    hipLaunchKernelGGL((k_spmv_sym<ND, 4, 0, T>), dim3(resident_grid(h, k_spmv_sym<ND, 4, 0, T>)), dim3(kThreads),  \
+                       0, s, g.Nn, g.node_ptr, g.up_base, g.node_nb, g.lo_val, values, x, y, nullptr, alpha, beta,  \
+                       nullptr, nullptr, 0)
+    if (g.nd == 1) FEM_SYM0(1);
+    else FEM_SYM0(3);
+#undef FEM_SYM0
+    FEM_HIP(hipGetLastError());
+}
+template void launch_spmv_sym<float>(const fem_handle *, const float *, const float *, float *, float, float,
+                                     hipStream_t);
+template void launch_spmv_sym<double>(const fem_handle *, const double *, const double *, double *, double, double,
+                                      hipStream_t);
+
+template <typename T>
 void kry_bicg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s) {
     hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 0, b, k.x, k.r, k.rh, k.p,
                        k.v, k.dinv, k.partials, k.sc, rtol);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kThreads), 0, s, krylov_grid(h), k.partials, k.sc, rtol);
     FEM_HIP(hipGetLastError());
 }
 
@@ -683,6 +808,7 @@ void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double
     // CG keeps z in the slot of rh
     hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 1, b, k.x, k.r, k.rh, k.p,
                        k.v, k.dinv, k.partials, k.sc, rtol);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kThreads), 0, s, krylov_grid(h), k.partials, k.sc, rtol);
     FEM_HIP(hipGetLastError());
 }
 
@@ -690,27 +816,26 @@ template <int ND, int P, int MODE, typename T>
 static void kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
                             const T *values, hipStream_t s) {
     const Graph &g = h->g;
-    hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T>), dim3(resident_grid(h, k_spmv_nodes<ND, P, MODE, T>)),
-                       dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values, x, y, w0, T(1), T(0), k.partials,
-                       k.sc, cg);
+    int G;
+    if (k.layout == LAYOUT_SYM) {
+        G = resident_grid(h, k_spmv_sym<ND, P, MODE, T>);
+        hipLaunchKernelGGL((k_spmv_sym<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.up_base,
+                           g.node_nb, g.lo_val, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
+    } else {
+        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T>);
+        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
+                           g.node_nb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
+    }
+    if (MODE == 1) hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc, cg);
+    else hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc);
 }
 
 template <typename T, int MODE>
 static void kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
                      const T *values, hipStream_t s) {
-    // nodes in flight per 32-lane group (tuning knob reused from the group setting)
-    const int P = h->spmv_group <= 4 ? 1 : (h->spmv_group == 8 ? 2 : (h->spmv_group == 16 ? 4 : 8));
-    if (h->g.nd == 1) {
-        if (P == 1) kry_spmv_launch<1, 1, MODE, T>(h, x, y, w0, k, cg, values, s);
-        else if (P == 2) kry_spmv_launch<1, 2, MODE, T>(h, x, y, w0, k, cg, values, s);
-        else if (P == 4) kry_spmv_launch<1, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
-        else kry_spmv_launch<1, 8, MODE, T>(h, x, y, w0, k, cg, values, s);
-    } else {
-        if (P == 1) kry_spmv_launch<3, 1, MODE, T>(h, x, y, w0, k, cg, values, s);
-        else if (P == 2) kry_spmv_launch<3, 2, MODE, T>(h, x, y, w0, k, cg, values, s);
-        else if (P == 4) kry_spmv_launch<3, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
-        else kry_spmv_launch<3, 8, MODE, T>(h, x, y, w0, k, cg, values, s);
-    }
+    // nodes in flight per 32-lane group
+    if (h->g.nd == 1) kry_spmv_launch<1, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
+    else kry_spmv_launch<3, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
 }
 
 template <typename T>
@@ -727,6 +852,7 @@ void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, h
     kry_spmv<T, 2>(h, k.sh, k.t, k.s, k, 0, A, s);
     if (ev) FEM_HIP(hipEventRecord(ev[3], s));
     hipLaunchKernelGGL((k_bicg_xr<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.ph, k.s, k.sh, k.t, k.partials, k.sc);
+    hipLaunchKernelGGL(k_fin_bicg_xr, dim3(1), blk, 0, s, int(grid.x), k.partials, k.sc);
     FEM_HIP(hipGetLastError());
 }
 
@@ -740,6 +866,7 @@ void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hip
     kry_spmv<T, 1>(h, k.p, k.v, k.p, k, 1, A, s);
     if (ev) FEM_HIP(hipEventRecord(ev[1], s));
     hipLaunchKernelGGL((k_cg_xr<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.p, k.v, k.dinv, k.partials, k.sc);
+    hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), blk, 0, s, int(grid.x), k.partials, k.sc);
     hipLaunchKernelGGL((k_cg_p<T>), grid, blk, 0, s, N, k.rh, k.p, k.sc);
     FEM_HIP(hipGetLastError());
 }
@@ -758,9 +885,9 @@ template void launch_spmv<float>(const fem_handle *, const float *, int, const f
 template void launch_spmv<double>(const fem_handle *, const double *, int, const double *, double *, double, double,
                                   hipStream_t);
 
-void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, unsigned *counter,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_self, dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, r, partials, out, counter);
+void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_self, dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, r, partials);
+    hipLaunchKernelGGL(k_fin_dot, dim3(1), dim3(kThreads), 0, s, krylov_grid(h), partials, out);
     FEM_HIP(hipGetLastError());
 }
 

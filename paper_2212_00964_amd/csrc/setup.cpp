@@ -137,6 +137,21 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     }
     row_ptr[g.N] = g.nnz;
 
+    // symmetric block layout: the upper blocks of node n are the tail of its sorted
+    // neighbour list, starting at the diagonal block
+    std::vector<int64_t> up_base(Nn + 1, 0);
+    for (int64_t n = 0; n < Nn; ++n) up_base[n + 1] = up_base[n] + (node_ptr[n + 1] - bdiag[n]);
+    std::vector<int32_t> lo_val(nnzb, -1);
+    parallel_for(Nn, [&](int64_t b, int64_t e) {
+        for (int64_t n = b; n < e; ++n)
+            for (int64_t k = node_ptr[n]; k < bdiag[n]; ++k) {  // lower blocks (n, m), m < n
+                const int64_t m = node_nb[k];
+                lo_val[k] = int32_t(up_base[m] + (mirror[k] - bdiag[m]));
+            }
+    });
+    g.nnzb_up = up_base[Nn];
+    g.up_base = upload(h, up_base);
+    g.lo_val = upload(h, lo_val);
     g.node_ptr = upload(h, node_ptr);
     g.node_nb = upload(h, node_nb);
     g.blk_row = upload(h, blk_row);

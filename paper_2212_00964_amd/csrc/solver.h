@@ -12,7 +12,6 @@ struct SolveWork {
     void *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr,
          *ph = nullptr, *sh = nullptr, *dinv = nullptr;
     double *partials = nullptr, *norm_partials = nullptr, *norm_out = nullptr;
-    unsigned *norm_counter = nullptr;
     KrylovScalars *sc = nullptr;
 };
 

@@ -22,6 +22,7 @@ FEM_OK = 0
 ERRORS = {-1: "FEM_EINVAL", -2: "FEM_ERANGE", -3: "FEM_EHIP", -4: "FEM_EMESH", -5: "FEM_EINVERTED",
           -6: "FEM_ENAN", -7: "FEM_EBREAKDOWN", -8: "FEM_EMAXITER", -9: "FEM_EDIVERGED", -10: "FEM_ENOMEM"}
 F32, F64 = 0, 1
+LAYOUT_CSR, LAYOUT_SYM_BLOCK = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 CG, BICGSTAB = 0, 1
 MAX_HIST = 64
@@ -76,8 +77,8 @@ class SolveStats(ctypes.Structure):
 
 # Names, in the order the header declares them (checked by the CPU test-suite).
 EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
-           "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv", "fem_apply_tangent",
-           "fem_newton_solve", "fem_adjoint_vjp"]
+           "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv",
+           "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp"]
 
 _lib = None
 
@@ -102,10 +103,11 @@ def lib():
         "fem_build_pattern": (ctypes.c_int, [P(MeshDesc), P(vp), P(i64), P(i64)]),
         "fem_destroy": (None, [vp]),
         "fem_pattern_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fem_values_count": (ctypes.c_int, [vp, i32, P(i64)]),
         "fem_load_vector": (ctypes.c_int, [vp, vp, vp]),
         "fem_workspace_bytes": (ctypes.c_int, [vp, P(SolveOpts), P(sz)]),
-        "fem_assemble": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, sz, vp]),
-        "fem_spmv": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, dbl, dbl, vp]),
+        "fem_assemble": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]),
+        "fem_spmv": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, dbl, dbl, vp]),
         "fem_apply_tangent": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "fem_newton_solve": (ctypes.c_int, [vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
         "fem_adjoint_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
@@ -233,7 +235,13 @@ class Problem:
         _check(lib().fem_load_vector(self.handle, _ptr(f), _stream()))
         return f
 
-    def assemble(self, u, theta=None, residual: bool = True, values_dtype: Optional[torch.dtype] = torch.float64):
+    def values_count(self, layout: int = LAYOUT_CSR) -> int:
+        c = ctypes.c_int64()
+        _check(lib().fem_values_count(self.handle, layout, ctypes.byref(c)))
+        return c.value
+
+    def assemble(self, u, theta=None, residual: bool = True, values_dtype: Optional[torch.dtype] = torch.float64,
+                 layout: int = LAYOUT_CSR):
         u = self._f64(u, self.n_dofs)
         theta = self.theta if theta is None else self._f64(theta, self.n_elems)
         r = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device) if residual else None
@@ -241,20 +249,20 @@ class Problem:
         dt = F64
         if values_dtype is not None:
             dt = F32 if values_dtype == torch.float32 else F64
-            vals = torch.empty(self.nnz, dtype=values_dtype, device=self.device)
+            vals = torch.empty(self.values_count(layout), dtype=values_dtype, device=self.device)
         ws = self.workspace(None)
-        _check(lib().fem_assemble(self.handle, _ptr(u), _ptr(theta), _ptr(r), _ptr(vals), dt, _ptr(ws),
+        _check(lib().fem_assemble(self.handle, _ptr(u), _ptr(theta), _ptr(r), _ptr(vals), dt, layout, _ptr(ws),
                                   ws.numel(), _stream()))
         return r, vals
 
     def spmv(self, values: torch.Tensor, x: torch.Tensor, transpose: bool = False, alpha: float = 1.0,
-             beta: float = 0.0, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+             beta: float = 0.0, y: Optional[torch.Tensor] = None, layout: int = LAYOUT_CSR) -> torch.Tensor:
         dt = F32 if values.dtype == torch.float32 else F64
-        if values.numel() != self.nnz or x.numel() != self.n_dofs or x.dtype != values.dtype:
+        if values.numel() != self.values_count(layout) or x.numel() != self.n_dofs or x.dtype != values.dtype:
             raise ValueError("spmv operand shapes/dtypes do not match the pattern")
         if y is None:
             y = torch.empty_like(x)
-        _check(lib().fem_spmv(self.handle, _ptr(values), dt, int(transpose), _ptr(x), _ptr(y), alpha, beta,
+        _check(lib().fem_spmv(self.handle, _ptr(values), dt, layout, int(transpose), _ptr(x), _ptr(y), alpha, beta,
                               _stream()))
         return y
 

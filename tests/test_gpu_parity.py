@@ -141,6 +141,56 @@ def test_spmv(dtype, transpose):
     prob.close()
 
 
+def sym_to_csr(pat, sym, nd):
+    """Expands the symmetric block layout (blocks (n, m), m >= n, CSR order of the node
+    graph, row-major) to full CSR values using only the oracle's pattern."""
+    N = pat.n
+    nn = N // nd
+    out = np.zeros(pat.nnz)
+    k = 0
+    up = {}
+    for n in range(nn):
+        r0 = pat.row_ptr[nd * n]
+        deg = (pat.row_ptr[nd * n + 1] - r0) // nd if nd > 1 else pat.row_ptr[n + 1] - r0
+        nbrs = pat.col_idx[r0:r0 + nd * deg:nd] // nd
+        for m in nbrs:
+            if m >= n:
+                up[(n, int(m))] = sym[k * nd * nd:(k + 1) * nd * nd].reshape(nd, nd)
+                k += 1
+    assert k * nd * nd == sym.size
+    for n in range(nn):
+        for i in range(nd):
+            r = nd * n + i
+            for pos in range(pat.row_ptr[r], pat.row_ptr[r + 1]):
+                c = pat.col_idx[pos]
+                m, kk = divmod(int(c), nd)
+                out[pos] = up[(n, m)][i, kk] if m >= n else up[(m, n)][kk, i]
+    return out
+
+
+@pytest.mark.parametrize("name", ["poisson-5x4x3-distorted", "nh-5x3x7-lognormal", "cantilever-7x3x5-distorted"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_symmetric_block_layout_assembly_and_spmv(name, dtype):
+    p = CASES[name]
+    u = _state(p, 2)
+    pat = orc.Pattern(p)
+    _, K_ref = orc.assemble(p, pat, u)
+    prob = fem.Problem(p, DEV)
+    _, Ks = prob.assemble(u, residual=False, values_dtype=dtype, layout=fem.LAYOUT_SYM_BLOCK)
+    assert Ks.numel() < prob.nnz
+    full = sym_to_csr(pat, host(Ks).astype(np.float64), p.ndpn)
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    assert rel(full, K_ref) <= tol
+    x = np.random.default_rng(8).standard_normal(p.n_dofs)
+    y0 = np.random.default_rng(9).standard_normal(p.n_dofs)
+    y = torch.as_tensor(y0, dtype=dtype, device=DEV)
+    prob.spmv(Ks, torch.as_tensor(x, dtype=dtype, device=DEV), alpha=-0.5, beta=2.0, y=y,
+              layout=fem.LAYOUT_SYM_BLOCK)
+    expect = -0.5 * (pat.matrix(K_ref) @ x) + 2.0 * y0
+    assert rel(host(y), expect) <= (1e-13 if dtype == torch.float64 else 5e-6)
+    prob.close()
+
+
 @pytest.mark.parametrize("name", ["cantilever-7x3x5-distorted", "nh-5x3x7-lognormal", "poisson-5x4x3-distorted"])
 def test_apply_tangent_matches_assembled_operator(name):
     p = CASES[name]
