@@ -17,6 +17,7 @@ J = 1/2 |u_free|^2.  Inputs are resident in HBM before the timed region.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,6 +43,30 @@ def spmv_bytes(prob, value_bytes):
     nd = prob.spec.ndpn
     n_blocks = prob.nnz // (nd * nd)
     return prob.nnz * value_bytes + n_blocks * 4 + (prob.spec.n_nodes + 1) * 8 + 3 * prob.n_dofs * value_bytes
+
+
+SPMV_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_nodes_nh_tensile_100x100x100.md")
+SPMV_SOURCES = ("paper_2212_00964_amd/csrc/linalg.hip", "paper_2212_00964_amd/csrc/internal.h")
+
+
+def measured_traffic(nx, ny, nz, precision):
+    """HBM bytes per SpMV launch from the committed FETCH_SIZE/WRITE_SIZE summary, or
+    None when the summary does not cover this run (other size or precision) or the
+    kernel sources changed since the counters were taken."""
+    if (nx, ny, nz) != (100, 100, 100) or precision != "mixed" or not os.path.exists(SPMV_PROFILE):
+        return None
+    fields = {}
+    for line in open(SPMV_PROFILE):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.split()[0] if v.split() else ""
+    h = hashlib.sha256()
+    for f in SPMV_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(gpu_counts, size_z=20, method="cg"):
@@ -197,7 +222,8 @@ def main():
         "krylov": args.krylov, "krylov_rtol": args.krylov_rtol, "adjoint_rtol": args.adjoint_rtol,
         "krylov_its": {"newton": int(np.median(kits_n)), "adjoint": int(np.median(kits_a))},
         "roofline": {"bound": "hbm", "kernel": "k_spmv_nodes (fused Krylov SpMV + FP64 dot)", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(nx, ny, nz, args.precision),
                      "avg_launch_us": avg_spmv_ms * 1e3, "launches": spmv_calls, "bytes_per_launch": nbytes},
     }
 
@@ -207,6 +233,21 @@ def main():
                                                                 krylov_rtol=1e-8, adjoint_rtol=1e-11),
                                        want_lambda=False)
         out["grad_rel_err_vs_fp64"] = float(torch.linalg.norm(g_step - g_ref) / torch.linalg.norm(g_ref))
+        # the same step in the plain FP64 form (same Krylov method and tolerances)
+        f_step = prob.opts(precision=fem.PREC_FP64, krylov=kry, n_load_steps=1, newton_fixed_its=1,
+                           krylov_rtol=args.krylov_rtol)
+        f_adj = prob.opts(precision=fem.PREC_FP64, krylov=kry, krylov_rtol=args.krylov_rtol,
+                          adjoint_rtol=args.adjoint_rtol)
+        for _ in range(2):
+            _, sf = prob.newton_solve(u0=u4, opts=f_step)
+            g_f, _, sfa = prob.adjoint_vjp(u5, dJdu, opts=f_adj, want_lambda=False)
+        out["fp64_step"] = {
+            "newton_step_ms": sf.ms_total, "adjoint_grad_ms": sfa.ms_total, "value_ms": sf.ms_total + sfa.ms_total,
+            "krylov_its": {"newton": sf.krylov_its_total, "adjoint": sfa.krylov_its_total},
+            "grad_rel_err_vs_fp64_ref": float(torch.linalg.norm(g_f - g_ref) / torch.linalg.norm(g_ref)),
+            "speedup_mixed_over_fp64": (sf.ms_total + sfa.ms_total) / (t_newton + t_adj)}
+        log(f"fp64 step: newton {sf.ms_total:.1f} ms, adjoint {sfa.ms_total:.1f} ms, "
+            f"speedup of mixed {out['fp64_step']['speedup_mixed_over_fp64']:.2f}x")
         u_ref, _ = prob.newton_solve(opts=prob.opts(precision=fem.PREC_FP64, krylov=fem.CG, krylov_rtol=1e-8,
                                                     newton_rtol=1e-11))
         res = {}
