@@ -46,7 +46,8 @@ def spmv_bytes(prob, value_bytes):
 
 
 SPMV_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_nodes_nh_tensile_100x100x100.md")
-SPMV_SOURCES = ("paper_2212_00964_amd/csrc/linalg.hip", "paper_2212_00964_amd/csrc/internal.h")
+SPMV_SOURCES = ("paper_2212_00964_amd/csrc/linalg.hip", "paper_2212_00964_amd/csrc/internal.h",
+                "paper_2212_00964_amd/csrc/lanes.h")
 
 
 def measured_traffic(nx, ny, nz, precision):
@@ -123,7 +124,9 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--krylov", choices=["cg", "bicgstab"], default="cg")
     ap.add_argument("--krylov-rtol", type=float, default=1e-3)
-    ap.add_argument("--adjoint-rtol", type=float, default=1e-6)
+    ap.add_argument("--adjoint-rtol", type=float, default=1e-5,
+                    help="relative FP64 residual of the adjoint solve; 1e-5 keeps the gradient within ~1e-7 of "
+                         "a tight FP64 gradient on this workload (the JSON line reports the measured error)")
     ap.add_argument("--no-compare", action="store_true", help="skip the full FP64-vs-mixed 5-step solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",

@@ -16,6 +16,7 @@
 // Paper: element residual R_e and K_e = dr_e/dU_e (Sec. 2.2), constitutive laws
 // (Sec. 2.3, Eq. (linear_elasticity), Eq. (neo-hookean)), assembly (Alg. 1).
 #include "internal.h"
+#include "lanes.h"
 
 namespace fem {
 
@@ -30,12 +31,10 @@ __device__ __forceinline__ int ref_sign(int a, int j) {
     return bit ? 1 : -1;
 }
 
+// Sum over the 8 lanes of an element (DPP butterfly; every lane gets the total).
 template <typename T>
 __device__ __forceinline__ T sum8(T v) {
-    v += __shfl_xor(v, 1, 8);
-    v += __shfl_xor(v, 2, 8);
-    v += __shfl_xor(v, 4, 8);
-    return v;
+    return lane_sum8(v);
 }
 
 template <typename T>

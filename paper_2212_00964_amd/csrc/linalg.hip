@@ -5,7 +5,7 @@
 // blocks in the same order.  The SpMV therefore walks the node graph (one 32-bit
 // column index per ND x ND block) instead of the scalar column array: a group of 32
 // lanes owns one node, lane l takes the l-th neighbour block, and the ND row sums
-// are finished with a 32-lane butterfly.
+// are finished with a 32-lane reduction built from cross-lane register moves.
 //
 // Krylov kernels are persistent (a fixed grid of blocks walking contiguous node
 // ranges), so their FP64 inner products reduce deterministically: per-block partial
@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "lanes.h"
 
 namespace fem {
 
@@ -171,9 +172,11 @@ __device__ __forceinline__ bool stopped(const KrylovScalars *sc) { return sc->co
 // Persistent SpMV over this block's contiguous node range.  The range's row
 // pointers are staged in LDS once; each 32-lane group then takes P nodes at a time
 // and issues all their column-index and value loads before any of them is used, so
-// a wave keeps P times more HBM traffic in flight than a one-node-at-a-time walk.
+// a wave keeps P times more HBM traffic in flight than a one-node-at-a-time walk,
+// and the next P nodes' loads are issued before the current x gathers are awaited.
 // Lane l of a group handles neighbour block l of each of its nodes (node degrees
-// above 32 fall back to a strided loop).
+// above 32 fall back to a strided loop); the ND row sums are finished with a
+// reduce-scatter over the group (a row swap and four DPP steps, no LDS traffic).
 //
 // MODE 0: y = alpha K x + beta y
 // MODE 1: y = K x and alpha = rho / (w0, y)                 (BiCGSTAB v = K ph, CG q = K p)
@@ -181,99 +184,114 @@ __device__ __forceinline__ bool stopped(const KrylovScalars *sc) { return sc->co
 constexpr int kSpmvGroup = 32;
 constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
 
+// Nodes in flight per 32-lane group: as many as fit with the double-buffered loads
+// at an occupancy of four (FP32) or two (FP64) wavefronts per SIMD.
+template <int ND, typename T>
+constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2); }
+
 template <int ND, int P, int MODE, typename T>
-__global__ __launch_bounds__(kThreads) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                          const int32_t *__restrict__ node_nb,
                                                          const T *__restrict__ values, const T *__restrict__ x,
                                                          T *__restrict__ y, const T *__restrict__ w0, T alpha,
                                                          T beta, double *partials, KrylovScalars *sc, int cg) {
     constexpr int G = kSpmvGroup;
     constexpr int GPB = kThreads / G;  // groups per block
+    static_assert(G == 32 && (ND == 1 || ND == 3), "32-lane groups, 1 or 3 dofs per node");
     __shared__ int64_t sptr[kMaxChunk + 1];
     if (MODE != 0 && stopped(sc)) return;
     int64_t r0, r1;
     block_range(Nn, r0, r1);
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
+    // after the group reduction, lanes 0, 8, 16 hold rows 0, 1, 2 of the node
+    const int row = (lane & 7) == 0 && lane < 8 * ND ? lane / 8 : -1;
     double d0 = 0.0, d1 = 0.0;
     for (int64_t n0 = r0; n0 < r1; n0 += kMaxChunk) {
-    const int cnt = int(r1 - n0 < kMaxChunk ? r1 - n0 : kMaxChunk);
-    __syncthreads();  // previous sub-chunk finished with sptr
-    for (int i = threadIdx.x; i <= cnt; i += kThreads) sptr[i] = node_ptr[n0 + i];
-    __syncthreads();
-    for (int base = grp; base < cnt; base += P * GPB) {
+        const int cnt = int(r1 - n0 < kMaxChunk ? r1 - n0 : kMaxChunk);
+        __syncthreads();  // previous sub-chunk finished with sptr
+        for (int i = threadIdx.x; i <= cnt; i += kThreads) sptr[i] = node_ptr[n0 + i];
+        __syncthreads();
         int64_t b0[P];
         int deg[P];
         int32_t m[P];
         T v[P][ND][ND];
-        T xm[P][ND];
+        // Column indices and values of P nodes.  Addresses are clamped (a slot past the
+        // chunk re-reads its last node, a lane past the degree reads block 0), so the
+        // loads are branch-free; the results of such slots are masked.
+        auto load_batch = [&](int base) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int ln = base + p * GPB;
-            const bool ok = ln < cnt;
-            b0[p] = ok ? sptr[ln] : 0;
-            deg[p] = ok ? int(sptr[ln + 1] - sptr[ln]) : 0;
-        }
-        // Loads are unconditional (inactive lanes read block 0 of their node, which
-        // always exists) so they stay branch-free and vectorised; results are masked.
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int lc = lane < deg[p] ? lane : 0;
-            m[p] = __builtin_nontemporal_load(node_nb + b0[p] + lc);
-            const T *vb = values + int64_t(ND) * ND * b0[p] + ND * lc;
-#pragma unroll
-            for (int i = 0; i < ND; ++i)
-#pragma unroll
-                for (int k = 0; k < ND; ++k) v[p][i][k] = __builtin_nontemporal_load(vb + int64_t(i) * ND * deg[p] + k);
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int k = 0; k < ND; ++k) xm[p][k] = x[int64_t(ND) * m[p] + k];
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-            if (!(lane < deg[p]))
-#pragma unroll
-                for (int k = 0; k < ND; ++k) xm[p][k] = T(0);
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            T acc[ND];
-#pragma unroll
-            for (int i = 0; i < ND; ++i) {
-                T a = T(0);
-#pragma unroll
-                for (int k = 0; k < ND; ++k) a += v[p][i][k] * xm[p][k];
-                acc[i] = lane < deg[p] ? a : T(0);
-            }
-            for (int l = lane + G; l < deg[p]; l += G) {  // high-degree nodes
-                const int64_t mm = node_nb[b0[p] + l];
-                const T *vb = values + int64_t(ND) * ND * b0[p] + ND * l;
+            for (int p = 0; p < P; ++p) {
+                int ln = base + p * GPB;
+                ln = ln < cnt ? ln : cnt - 1;
+                b0[p] = sptr[ln];
+                deg[p] = int(sptr[ln + 1] - b0[p]);
+                const int lc = lane < deg[p] ? lane : 0;
+                m[p] = __builtin_nontemporal_load(node_nb + b0[p] + lc);
+                const T *vb = values + int64_t(ND) * ND * b0[p] + ND * lc;
 #pragma unroll
                 for (int i = 0; i < ND; ++i)
 #pragma unroll
-                    for (int k = 0; k < ND; ++k) acc[i] += vb[int64_t(i) * ND * deg[p] + k] * x[ND * mm + k];
+                    for (int k = 0; k < ND; ++k)
+                        v[p][i][k] = __builtin_nontemporal_load(vb + int64_t(i) * ND * deg[p] + k);
             }
+        };
+        load_batch(grp);
+        for (int base = grp; base < cnt; base += P * GPB) {
+            // Software pipeline: the x gathers of this batch go out first, then the next
+            // batch's index and value loads, so waiting for the gathers leaves the next
+            // batch in flight (memory counters complete in issue order).
+            T xm[P][ND], cv[P][ND][ND];
+            int cdeg[P];
+            int64_t cb0[P];
 #pragma unroll
-            for (int i = 0; i < ND; ++i) acc[i] = group_sum<G>(acc[i]);
-            const int ln = base + p * GPB;
-            if (ln < cnt && lane < ND) {
-                T sv = acc[0];
+            for (int p = 0; p < P; ++p) {
 #pragma unroll
-                for (int i = 1; i < ND; ++i)
-                    if (lane == i) sv = acc[i];
-                const int64_t d = int64_t(ND) * (n0 + ln) + lane;
-                if (MODE == 0) {
-                    T out = alpha * sv;
-                    if (beta != T(0)) out += beta * y[d];
-                    y[d] = out;
-                } else {
-                    y[d] = sv;
-                    d0 += double(w0[d]) * double(sv);
-                    if (MODE == 2) d1 += double(sv) * double(sv);
+                for (int k = 0; k < ND; ++k) xm[p][k] = x[int64_t(ND) * m[p] + k];
+                cdeg[p] = deg[p];
+                cb0[p] = b0[p];
+#pragma unroll
+                for (int i = 0; i < ND; ++i)
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) cv[p][i][k] = v[p][i][k];
+            }
+            load_batch(base + P * GPB);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                T acc[ND];
+#pragma unroll
+                for (int i = 0; i < ND; ++i) {
+                    T a = T(0);
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) a += cv[p][i][k] * xm[p][k];
+                    acc[i] = lane < cdeg[p] ? a : T(0);
+                }
+                for (int l = lane + G; l < cdeg[p]; l += G) {  // nodes with more than 32 neighbours
+                    const int64_t mm = node_nb[cb0[p] + l];
+                    const T *vb = values + int64_t(ND) * ND * cb0[p] + ND * l;
+#pragma unroll
+                    for (int i = 0; i < ND; ++i)
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) acc[i] += vb[int64_t(i) * ND * cdeg[p] + k] * x[ND * mm + k];
+                }
+                T sv;
+                if constexpr (ND == 3) sv = group32_sum3(acc[0], acc[1], acc[2], lane);
+                else sv = group32_sum(acc[0], lane);
+                const int ln = base + p * GPB;
+                if (ln < cnt && row >= 0) {
+                    const int64_t d = int64_t(ND) * (n0 + ln) + row;
+                    if (MODE == 0) {
+                        T out = alpha * sv;
+                        if (beta != T(0)) out += beta * y[d];
+                        y[d] = out;
+                    } else {
+                        y[d] = sv;
+                        d0 += double(w0[d]) * double(sv);
+                        if (MODE == 2) d1 += double(sv) * double(sv);
+                    }
                 }
             }
         }
-    }
     }
     if constexpr (MODE != 0) {
         double vv[2] = {d0, d1};
@@ -742,7 +760,8 @@ static void spmv_launch(const fem_handle *h, const T *values, int transpose, con
         hipLaunchKernelGGL((k_spmv<ND, G, true, T>), grid, dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, g.mirror,
                            values, x, y, alpha, beta);
     else
-        hipLaunchKernelGGL((k_spmv_nodes<ND, 4, 0, T>), dim3(resident_grid(h, k_spmv_nodes<ND, 4, 0, T>)),
+        hipLaunchKernelGGL((k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T>),
+                           dim3(resident_grid(h, k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T>)),
                            dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values, x, y, nullptr, alpha, beta,
                            nullptr, nullptr, 0);
 }
@@ -834,8 +853,8 @@ template <typename T, int MODE>
 static void kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
                      const T *values, hipStream_t s) {
     // nodes in flight per 32-lane group
-    if (h->g.nd == 1) kry_spmv_launch<1, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
-    else kry_spmv_launch<3, 4, MODE, T>(h, x, y, w0, k, cg, values, s);
+    if (h->g.nd == 1) kry_spmv_launch<1, spmv_batch<1, T>(), MODE, T>(h, x, y, w0, k, cg, values, s);
+    else kry_spmv_launch<3, spmv_batch<3, T>(), MODE, T>(h, x, y, w0, k, cg, values, s);
 }
 
 template <typename T>
