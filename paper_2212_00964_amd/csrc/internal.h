@@ -47,6 +47,9 @@ struct KrylovScalars {
     double rmin2;    // smallest |r|^2 reached so far
     int its, converged, breakdown;
     int restart_at;  // BiCGSTAB restarts (rhat = p = r) at the iteration with this index
+    // CG: rho of iteration k lives in rho_pp[k & 1], so a kernel that publishes the
+    // next rho never overwrites the value its other blocks are still reading
+    double rho_pp[2];
 };
 constexpr size_t kScalarsHostBytes = sizeof(KrylovScalars);
 
@@ -143,7 +146,8 @@ struct KrylovVecs {
     const T *A;  // values of the operator
     int layout;  // LAYOUT_CSR or LAYOUT_SYM
     T *x, *r, *rh, *p, *v, *s, *t, *ph, *sh, *dinv;
-    double *partials;
+    double *partials;   // per-block partial sums written by one kernel ...
+    double *partials2;  // ... and by the next one (the two alternate)
     KrylovScalars *sc;
 };
 
@@ -153,8 +157,9 @@ template <typename T>
 void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
 template <typename T>
 void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
+// CG iteration number `it` (0-based within this solve).
 template <typename T>
-void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
+void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev);
 
 // Vector helpers.
 void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, hipStream_t s);

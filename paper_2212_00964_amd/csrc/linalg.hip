@@ -7,11 +7,11 @@
 // lanes owns one node, lane l takes the l-th neighbour block, and the ND row sums
 // are finished with a 32-lane reduction built from cross-lane register moves.
 //
-// Krylov kernels are persistent (a fixed grid of blocks walking contiguous node
-// ranges), so their FP64 inner products reduce deterministically: per-block partial
-// sums in a fixed lane order, then the last block to finish sums the partials in
-// block order and updates the scalars of the method on the device.  The host only
-// reads the convergence flag every few iterations.
+// Krylov inner products are FP64 and deterministic: every block stores its partial
+// sum (fixed lane order), and the next kernel sums the partials in block order,
+// either in a one-block finalize kernel or redundantly in every block of the next
+// vector kernel (CG).  Scalars of the method live on the device; the host only reads
+// the convergence flag every few iterations.
 //
 // Paper: BiCGSTAB with a Jacobi preconditioner is the linear solver inside Newton
 // (Sec. 5, item 2; van der Vorst 1992).
@@ -519,14 +519,28 @@ __global__ __launch_bounds__(kThreads) void k_fin_bicg_xr(int G, const double *_
     }
 }
 
-// CG: x += alpha p; r -= alpha q; z = Dinv r; rho_new = (r, z); |r|^2; beta = rho_new / rho
+// CG with the scalar updates folded into the vector kernels.  Each block sums the
+// previous kernel's per-block partials itself (same order in every block, so all
+// blocks agree bit for bit), which removes the one-block finalize launches.
+//
+// Iteration it: alpha = rho_pp[it & 1] / (p, q) with q = K p from the SpMV partials;
+// x += alpha p; r -= alpha q; z = Dinv r; partials of (r, z) and |r|^2.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_xr(int64_t N, T *__restrict__ x, T *__restrict__ r,
-                                                    T *__restrict__ z, const T *__restrict__ p,
-                                                    const T *__restrict__ q, const T *__restrict__ dinv,
-                                                    double *partials, KrylovScalars *sc) {
+__global__ __launch_bounds__(kThreads) void k_cg_xr_fused(int64_t N, T *__restrict__ x, T *__restrict__ r,
+                                                          T *__restrict__ z, const T *__restrict__ p,
+                                                          const T *__restrict__ q, const T *__restrict__ dinv,
+                                                          const double *__restrict__ pq_partials, int pq_count,
+                                                          double *partials, KrylovScalars *sc, int it) {
     if (stopped(sc)) return;
-    const T al = T(sc->alpha);
+    double pq[1];
+    sum_partials<1>(pq_partials, pq_count, pq);
+    if (!(pq[0] > 0.0) || !isfinite(pq[0])) {  // CG needs (p, K p) > 0
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->breakdown = 1;
+        return;
+    }
+    const double alpha = sc->rho_pp[it & 1] / pq[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
+    const T al = T(alpha);
     double d0 = 0.0, d1 = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
         x[i] += al * p[i];
@@ -541,29 +555,31 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr(int64_t N, T *__restrict__ x
     block_store_partials<2>(v, partials);
 }
 
-// CG: rho_new = (r, z), |r|^2, beta = rho_new / rho, convergence test
-__global__ __launch_bounds__(kThreads) void k_fin_cg_xr(int G, const double *__restrict__ partials,
-                                                        KrylovScalars *sc) {
+// rho = (r, z), |r|^2 from the partials; convergence test; beta = rho / rho_pp[it & 1];
+// p = z + beta p.  Block 0 publishes the scalars (the new rho to the other slot).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_p_fused(int64_t N, const T *__restrict__ z, T *__restrict__ p,
+                                                         const double *__restrict__ rz_partials, int rz_count,
+                                                         KrylovScalars *sc, int it) {
     if (stopped(sc)) return;
     double tot[2];
-    sum_partials<2>(partials, G, tot);
-    if (threadIdx.x == 0) {
-        sc->rho_old = sc->rho;
+    sum_partials<2>(rz_partials, rz_count, tot);
+    const double rho_prev = sc->rho_pp[it & 1];
+    const bool nan = !isfinite(tot[0]) || !isfinite(tot[1]);
+    const bool conv = !nan && tot[1] <= sc->tol2;
+    const double beta = tot[0] / rho_prev;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho_old = rho_prev;
         sc->rho = tot[0];
-        sc->beta = tot[0] / sc->rho_old;
+        sc->rho_pp[(it + 1) & 1] = tot[0];
+        sc->beta = beta;
         sc->rnorm2 = tot[1];
-        sc->its += 1;
-        if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->breakdown = 2;
-        else if (tot[1] <= sc->tol2) sc->converged = 1;
+        sc->its = it + 1;
+        if (nan) sc->breakdown = 2;
+        else if (conv) sc->converged = 1;
     }
-}
-
-// CG: p = z + beta p
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_p(int64_t N, const T *__restrict__ z, T *__restrict__ p,
-                                                   const KrylovScalars *sc) {
-    if (stopped(sc)) return;
-    const T bt = T(sc->beta);
+    if (nan || conv) return;
+    const T bt = T(beta);
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
         p[i] = z[i] + bt * p[i];
 }
@@ -604,6 +620,8 @@ __global__ __launch_bounds__(kThreads) void k_fin_init(int G, const double *__re
     sum_partials<2>(partials, G, tot);
     if (threadIdx.x == 0) {
         sc->rho = tot[0];
+        sc->rho_pp[0] = tot[0];
+        sc->rho_pp[1] = tot[0];
         sc->rho_old = 1.0;
         sc->alpha = 1.0;
         sc->omega = 1.0;
@@ -738,6 +756,10 @@ int krylov_grid(const fem_handle *h) {
     return 8 * h->num_cus;
 }
 
+// Grid of the fused CG vector kernels: every block also sums the previous kernel's
+// partials, so fewer, fuller blocks (4 per CU) keep that redundant work small.
+static int krylov_vec_grid(const fem_handle *h) { return 4 * h->num_cus; }
+
 // Persistent grid of a kernel: the blocks that can be resident at once (runtime
 // occupancy of this kernel variant), a multiple of the 8 XCDs.
 template <typename K>
@@ -831,9 +853,11 @@ void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double
     FEM_HIP(hipGetLastError());
 }
 
+// Launches the fused SpMV (partials into k.partials) and, unless the caller folds it
+// into its next kernel, the one-block finalize; returns the SpMV grid size.
 template <int ND, int P, int MODE, typename T>
-static void kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
-                            const T *values, hipStream_t s) {
+static int kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
+                           const T *values, bool finalize, hipStream_t s) {
     const Graph &g = h->g;
     int G;
     if (k.layout == LAYOUT_SYM) {
@@ -845,16 +869,18 @@ static void kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, 
         hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
                            g.node_nb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
     }
-    if (MODE == 1) hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc, cg);
-    else hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc);
+    if (finalize) {
+        if (MODE == 1) hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc, cg);
+        else hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc);
+    }
+    return G;
 }
 
 template <typename T, int MODE>
-static void kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
-                     const T *values, hipStream_t s) {
-    // nodes in flight per 32-lane group
-    if (h->g.nd == 1) kry_spmv_launch<1, spmv_batch<1, T>(), MODE, T>(h, x, y, w0, k, cg, values, s);
-    else kry_spmv_launch<3, spmv_batch<3, T>(), MODE, T>(h, x, y, w0, k, cg, values, s);
+static int kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
+                    const T *values, hipStream_t s, bool finalize = true) {
+    if (h->g.nd == 1) return kry_spmv_launch<1, spmv_batch<1, T>(), MODE, T>(h, x, y, w0, k, cg, values, finalize, s);
+    return kry_spmv_launch<3, spmv_batch<3, T>(), MODE, T>(h, x, y, w0, k, cg, values, finalize, s);
 }
 
 template <typename T>
@@ -875,18 +901,22 @@ void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, h
     FEM_HIP(hipGetLastError());
 }
 
+// One CG iteration in three kernels: q = K p with (p, q) partials; the x/r/z update
+// with alpha taken from those partials; the p update with beta taken from the
+// (r, z) partials.  The two partial buffers alternate so that no kernel overwrites
+// partials that blocks of the same kernel are still reading.
 template <typename T>
-void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev) {
+void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev) {
     const int64_t N = h->g.N;
-    dim3 grid(krylov_grid(h)), blk(kThreads);
+    dim3 grid(krylov_vec_grid(h)), blk(kThreads);
     const T *A = k.A;
     // slots: z = rh, q = v
     if (ev) FEM_HIP(hipEventRecord(ev[0], s));
-    kry_spmv<T, 1>(h, k.p, k.v, k.p, k, 1, A, s);
+    const int G = kry_spmv<T, 1>(h, k.p, k.v, k.p, k, 1, A, s, false);
     if (ev) FEM_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((k_cg_xr<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.p, k.v, k.dinv, k.partials, k.sc);
-    hipLaunchKernelGGL(k_fin_cg_xr, dim3(1), blk, 0, s, int(grid.x), k.partials, k.sc);
-    hipLaunchKernelGGL((k_cg_p<T>), grid, blk, 0, s, N, k.rh, k.p, k.sc);
+    hipLaunchKernelGGL((k_cg_xr_fused<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.p, k.v, k.dinv, k.partials, G,
+                       k.partials2, k.sc, it);
+    hipLaunchKernelGGL((k_cg_p_fused<T>), grid, blk, 0, s, N, k.rh, k.p, k.partials2, int(grid.x), k.sc, it);
     FEM_HIP(hipGetLastError());
 }
 
@@ -897,8 +927,8 @@ template void kry_cg_init<float>(const fem_handle *, const KrylovVecs<float> &, 
 template void kry_cg_init<double>(const fem_handle *, const KrylovVecs<double> &, const double *, double, hipStream_t);
 template void kry_bicg_iter<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t, hipEvent_t *);
 template void kry_bicg_iter<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t, hipEvent_t *);
-template void kry_cg_iter<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t, hipEvent_t *);
-template void kry_cg_iter<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t, hipEvent_t *);
+template void kry_cg_iter<float>(const fem_handle *, const KrylovVecs<float> &, int, hipStream_t, hipEvent_t *);
+template void kry_cg_iter<double>(const fem_handle *, const KrylovVecs<double> &, int, hipStream_t, hipEvent_t *);
 template void launch_spmv<float>(const fem_handle *, const float *, int, const float *, float *, float, float,
                                  hipStream_t);
 template void launch_spmv<double>(const fem_handle *, const double *, int, const double *, double *, double, double,

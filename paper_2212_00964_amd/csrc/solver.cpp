@@ -85,6 +85,7 @@ static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_
     w.sh = v[8];
     w.dinv = v[9];
     w.partials = c.take<double>(2 * int64_t(krylov_grid(h)));
+    w.partials2 = c.take<double>(2 * int64_t(krylov_grid(h)));
     w.norm_partials = c.take<double>(krylov_grid(h));
     w.sc = c.take<KrylovScalars>(1);
     w.norm_out = c.take<double>(1);
@@ -136,6 +137,7 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
                     static_cast<T *>(w.sh),
                     static_cast<T *>(w.dinv),
                     w.partials,
+                    w.partials2,
                     w.sc};
     const bool cg = o.krylov == FEM_KRYLOV_CG;
     const T *b = static_cast<const T *>(w.b);
@@ -155,7 +157,7 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
     for (int it = 0;; it += every) {
         for (int j = 0; j < every; ++j) {
             hipEvent_t *e = prof ? &ev[4 * j] : nullptr;
-            if (cg) kry_cg_iter<T>(h, k, s, e);
+            if (cg) kry_cg_iter<T>(h, k, it + j, s, e);
             else kry_bicg_iter<T>(h, k, s, e);
         }
         FEM_HIP(hipMemcpyAsync(h->host_kry, w.sc, kScalarsHostBytes, hipMemcpyDeviceToHost, s));

@@ -11,7 +11,7 @@ struct SolveWork {
     void *ke = nullptr, *values = nullptr, *b = nullptr;
     void *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr,
          *ph = nullptr, *sh = nullptr, *dinv = nullptr;
-    double *partials = nullptr, *norm_partials = nullptr, *norm_out = nullptr;
+    double *partials = nullptr, *partials2 = nullptr, *norm_partials = nullptr, *norm_out = nullptr;
     KrylovScalars *sc = nullptr;
 };
 
