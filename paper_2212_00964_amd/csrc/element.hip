@@ -239,13 +239,15 @@ __device__ __forceinline__ void load_node(const double *coords, const int32_t *c
 // ------------------------------------------------------------------ residual-type kernels
 enum { VEC_RESIDUAL = 0, VEC_JVP = 1, VEC_VJP = 2, VEC_LIFT = 3 };
 
-// VEC_RESIDUAL: scratch[e][a][i] = sum_q detJ f(grad u) g_a            (modulus m(theta_e))
-// VEC_JVP:      scratch[e][a][i] = sum_q detJ (A(grad u) : grad v) g_a  (v with Dirichlet dofs zeroed)
+// (slot s = kpos[e*8 + a]: node-major incidence order, so each node's terms are contiguous)
+// VEC_RESIDUAL: scratch[s][i] = sum_q detJ f(grad u) g_a            (modulus m(theta_e))
+// VEC_JVP:      scratch[s][i] = sum_q detJ (A(grad u) : grad v) g_a  (v with Dirichlet dofs zeroed)
 // VEC_VJP:      g[e] = -m'(theta_e) sum_{a,i free} lam_a,i sum_q detJ f_unit(grad u) g_a
 // VEC_LIFT:     as VEC_JVP but with v used on every dof (v is nonzero on Dirichlet dofs only)
 template <int MODEL, int ND, int MODE>
 __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const double *__restrict__ coords,
                                                           const int32_t *__restrict__ conn,
+                                                          const int32_t *__restrict__ kpos,
                                                           const uint8_t *__restrict__ mask, Material mat,
                                                           const double *__restrict__ theta,
                                                           const double *__restrict__ u,
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
         if (id.valid && id.a == 0) out[id.e] = -dmodulus(mat, th) * s;
     } else if (id.valid) {
 #pragma unroll
-        for (int i = 0; i < ND; ++i) out[(id.e * 8 + id.a) * ND + i] = acc[i];
+        for (int i = 0; i < ND; ++i) out[int64_t(kpos[id.e * 8 + id.a]) * ND + i] = acc[i];
     }
 }
 
@@ -297,7 +299,6 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
 // VEC_LIFT:     out[d] = sum, 0 on Dirichlet dofs.
 template <int ND, int MODE>
 __global__ __launch_bounds__(256) void k_gather_vec(int64_t N, const int64_t *__restrict__ ne_ptr,
-                                                    const int32_t *__restrict__ ne_list,
                                                     const double *__restrict__ scratch,
                                                     const uint8_t *__restrict__ mask, const double *__restrict__ F,
                                                     double lf, const double *__restrict__ v,
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(256) void k_gather_vec(int64_t N, const int64_t *__
     int64_t n = d / ND;
     int i = int(d - n * ND);
     double s = 0.0;
-    for (int64_t k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) s += scratch[int64_t(ne_list[k]) * ND + i];
+    for (int64_t k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) s += scratch[k * ND + i];  // node n's contiguous slots
     double r;
     if (mask && mask[d]) {
         r = (MODE == VEC_JVP) ? v[d] : 0.0;
@@ -320,10 +321,12 @@ __global__ __launch_bounds__(256) void k_gather_vec(int64_t N, const int64_t *__
 
 // ------------------------------------------------------------------ tangent kernel
 // Lane a accumulates the row block K_e[(a,i), (b,k)] for all b, i, k and writes it to
-// scratch[((e*8 + a)*8 + b)*ND*ND + i*ND + k].
+// scratch[((kpos[e*8 + a])*8 + b)*ND*ND + i*ND + k]: the row blocks feeding node
+// conn[e][a] are contiguous, so the gather reads each node's 8 row blocks as one run.
 template <int MODEL, int ND, typename T>
 __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const double *__restrict__ coords,
-                                                              const int32_t *__restrict__ conn, Material mat,
+                                                              const int32_t *__restrict__ conn,
+                                                              const int32_t *__restrict__ kpos, Material mat,
                                                               const double *__restrict__ theta,
                                                               const double *__restrict__ u, T *__restrict__ ke,
                                                               int *status) {
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
     if (id.valid && id.a == 0 && (!mesh_ok || !mat_ok))
         atomicOr(status, (!mesh_ok ? ST_MESH : 0) | (!mat_ok ? ST_INVERTED : 0));
     if (id.valid) {
-        T *dst = ke + (id.e * 8 + id.a) * 8 * ND * ND;
+        T *dst = ke + int64_t(kpos[id.e * 8 + id.a]) * 8 * ND * ND;
 #pragma unroll
         for (int b = 0; b < 8; ++b)
 #pragma unroll
@@ -512,9 +515,9 @@ void launch_residual(const fem_handle *h, const double *u, const double *theta, 
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_RESIDUAL>), dim3(gridE), dim3(kThreads), 0, s, g.Ne,
-                           h->m.coords, h->m.conn, h->m.mask, h->mat, theta, u, nullptr, scratch, h->status);
+                           h->m.coords, h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, nullptr, scratch, h->status);
         hipLaunchKernelGGL((k_gather_vec<ND, VEC_RESIDUAL>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N,
-                           g.ne_ptr, g.ne_list, scratch, h->m.mask, h->m.fext, lf, nullptr, r, h->status);
+                           g.ne_ptr, scratch, h->m.mask, h->m.fext, lf, nullptr, r, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
@@ -529,9 +532,9 @@ void launch_apply_tangent(const fem_handle *h, const double *u, const double *th
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_JVP>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
-                           h->m.conn, h->m.mask, h->mat, theta, u, v, scratch, h->status);
+                           h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, v, scratch, h->status);
         hipLaunchKernelGGL((k_gather_vec<ND, VEC_JVP>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
-                           g.ne_list, scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
+                           scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
@@ -543,9 +546,9 @@ void launch_lift(const fem_handle *h, const double *u, const double *theta, cons
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_LIFT>), dim3(gridE), dim3(kThreads), 0, s, g.Ne,
-                           h->m.coords, h->m.conn, h->m.mask, h->mat, theta, u, v, scratch, h->status);
+                           h->m.coords, h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, v, scratch, h->status);
         hipLaunchKernelGGL((k_gather_vec<ND, VEC_LIFT>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
-                           g.ne_list, scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
+                           scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
@@ -557,7 +560,7 @@ void launch_vjp(const fem_handle *h, const double *u, const double *theta, const
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_VJP>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
-                           h->m.conn, h->m.mask, h->mat, theta, u, lam, gout, h->status);
+                           h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, lam, gout, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
@@ -570,7 +573,7 @@ void launch_tangent(const fem_handle *h, const double *u, const double *theta, T
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_tangent<MODEL, ND, T>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
-                           h->m.conn, h->mat, theta, u, ke, h->status);
+                           h->m.conn, g.kpos, h->mat, theta, u, ke, h->status);
         if (layout == LAYOUT_SYM)
             hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_SYM, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s,
                                g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, g.bdiag,

@@ -64,9 +64,11 @@ struct Graph {
     int32_t *mirror = nullptr;    // [nnzb] block (m, n) for block (n, m)
     int32_t *bdiag = nullptr;     // [Nn] block (n, n)
     int64_t *blk_ptr = nullptr;   // [nnzb+1] contributions of element-pair blocks
-    int32_t *blk_src = nullptr;   // [64*Ne] contribution e*64 + a*8 + b, element ascending
+    int32_t *blk_src = nullptr;   // [64*Ne] contribution kpos[e*8+a]*8 + b, element ascending
     int64_t *ne_ptr = nullptr;    // [Nn+1] node -> (element, local node) incidence
-    int32_t *ne_list = nullptr;   // [8*Ne] e*8 + a, element ascending
+    int32_t *kpos = nullptr;      // [8*Ne] slot of (e, a) in node-major incidence order
+                                  //        (node n owns slots ne_ptr[n] .. ne_ptr[n+1]-1,
+                                  //        element ascending)
     int32_t *bslot = nullptr;     // [Ne*64] block of local pair (a, b) of element e
     int64_t *row_ptr = nullptr;   // [N+1] scalar CSR row starts
     // Symmetric block layout: only blocks (n, m) with m >= n are stored, block-major

@@ -66,6 +66,11 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
         for (int64_t e = 0; e < Ne; ++e)
             for (int a = 0; a < 8; ++a) ne_list[fill[conn[8 * e + a]]++] = int32_t(e * 8 + a);
     }
+    // Element outputs are written in this node-major incidence order: (e, a) goes to
+    // slot kpos[e*8 + a], so the contributions of node n are the contiguous slots
+    // ne_ptr[n] .. ne_ptr[n+1] and the gathers read them as one run.
+    std::vector<int32_t> kpos(Ne * 8);
+    for (int64_t s = 0; s < Ne * 8; ++s) kpos[ne_list[s]] = int32_t(s);
 
     // neighbour sets: nodes sharing an element, ascending, unique
     std::vector<int64_t> node_ptr(Nn + 1, 0);
@@ -126,7 +131,8 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     std::vector<int32_t> blk_src(Ne * 64);
     {
         std::vector<int64_t> fill(blk_ptr.begin(), blk_ptr.end() - 1);
-        for (int64_t i = 0; i < Ne * 64; ++i) blk_src[fill[bslot[i]]++] = int32_t(i);
+        // contribution (e, a, b) lives in element row block kpos[e*8+a], column block b
+        for (int64_t i = 0; i < Ne * 64; ++i) blk_src[fill[bslot[i]]++] = kpos[i >> 3] * 8 + int32_t(i & 7);
     }
 
     // scalar CSR row starts: the nd rows of node n share the node's block list
@@ -160,7 +166,7 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     g.blk_ptr = upload(h, blk_ptr);
     g.blk_src = upload(h, blk_src);
     g.ne_ptr = upload(h, ne_ptr);
-    g.ne_list = upload(h, ne_list);
+    g.kpos = upload(h, kpos);
     g.bslot = upload(h, bslot);
     g.row_ptr = upload(h, row_ptr);
 }
