@@ -74,6 +74,10 @@ enum { FEM_LAYOUT_CSR = 0, FEM_LAYOUT_SYM_BLOCK = 1 };
  * and all Krylov inner products stay FP64. */
 enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
 enum { FEM_KRYLOV_CG = 0, FEM_KRYLOV_BICGSTAB = 1 };
+/* Krylov preconditioner.  FEM_PRECOND_JACOBI: the inverse diagonal of the tangent
+ * (the paper's Jacobi preconditioner, Sec. 5).  FEM_PRECOND_BLOCK_JACOBI: the
+ * inverse of each node's ndpn x ndpn diagonal block (equal to Jacobi when ndpn = 1). */
+enum { FEM_PRECOND_JACOBI = 0, FEM_PRECOND_BLOCK_JACOBI = 1 };
 
 typedef struct fem_handle fem_handle;
 
@@ -116,7 +120,7 @@ typedef struct {
     int32_t profile_spmv;   /* 1: time every Krylov SpMV launch with HIP events */
     int32_t newton_fixed_its; /* > 0: run exactly this many Newton iterations per load step
                                  (the first one being the lifted step), without a convergence test */
-    int32_t reserved;
+    int32_t precond;        /* FEM_PRECOND_JACOBI or FEM_PRECOND_BLOCK_JACOBI */
 } fem_solve_opts;
 
 #define FEM_MAX_HIST 64
@@ -223,6 +227,72 @@ int fem_newton_solve(fem_handle *h, double *u, const double *theta, const double
 int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *vjp_theta,
                     double *lambda_out, const fem_solve_opts *opts, fem_solve_stats *stats, void *workspace,
                     size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------------
+ * SIMP compliance optimisation (Sec. 4.2): the pieces around the gradient.  The
+ * loop is: solve, compliance C = F_ext . u, dC/dtheta by the adjoint (lambda = u
+ * for this self-adjoint objective) through fem_param_vjp, the sensitivity filter,
+ * and one MMA step (Svanberg 1987) under the material-fraction constraint.
+ * ---------------------------------------------------------------------------- */
+
+/* Per-element parameter VJP for a given adjoint state (no solve):
+ * vjp_theta[e] = -lambda^T dC/dtheta_e (Sec. 3, Eq. (adjoint_chain_simp)); entries
+ * of lambda on Dirichlet dofs are ignored.  u, lambda [N]; theta, vjp_theta
+ * [n_elems]; FP64 device pointers.  Asynchronous on `stream`. */
+int fem_param_vjp(fem_handle *h, const double *u, const double *theta, const double *lambda, double *vjp_theta,
+                  void *stream);
+
+/* Element volumes v_e = sum_q det J_q (2x2x2 Gauss, weights 1) [n_elems] FP64 into
+ * a caller device buffer; with normalized != 0 the fractions v_e / sum_f v_f (the
+ * gradient of the material fraction).  Blocks when normalized, else asynchronous. */
+int fem_element_volumes(fem_handle *h, double *volumes, int32_t normalized, void *stream);
+
+/* Builds the convolution filter of radius rmin > 0 over the element centroids (mean
+ * of the 8 node coordinates): weights H_ef = max(0, rmin - |c_e - c_f|).  The filter
+ * lives in the handle (a later call replaces it).  Synchronous.  FEM_EINVAL for
+ * rmin <= 0. */
+int fem_filter_setup(fem_handle *h, double rmin);
+
+/* FEM_FILTER_DENSITY:     out_e = sum_f H_ef x_f / sum_f H_ef
+ * FEM_FILTER_SENSITIVITY: out_e = sum_f H_ef theta_f x_f / (max(1e-3, theta_e) sum_f H_ef)
+ * (the sensitivity filter that blurs dC/dtheta against checkerboards).  x, out
+ * [n_elems] FP64 device (distinct buffers); theta is read only by the sensitivity
+ * filter.  FEM_EINVAL when fem_filter_setup was not called.  Asynchronous. */
+enum { FEM_FILTER_DENSITY = 0, FEM_FILTER_SENSITIVITY = 1 };
+int fem_filter_apply(fem_handle *h, int32_t mode, const double *theta, const double *x, double *out, void *stream);
+
+/* Scratch bytes of fem_dot and fem_mma_update for vectors of length n. */
+size_t fem_vector_workspace_bytes(int64_t n);
+
+/* Deterministic FP64 dot product sum_i a_i b_i of two device vectors of length n on
+ * the current device (fixed blocking, fixed summation order); the result goes to
+ * the host pointer `result`.  Blocks. */
+int fem_dot(const double *a, const double *b, int64_t n, double *result, void *workspace, size_t workspace_bytes,
+            void *stream);
+
+/* Method of moving asymptotes (Svanberg 1987), one constraint, box [xmin, xmax]:
+ * asymptotes at asy_init * box for the first two iterations, then moved by
+ * asy_decr (oscillating coordinate) or asy_incr (monotone) and kept between 0.01
+ * and 10 box widths from x; move limits albefa of the distance to the asymptote and
+ * `move` * box; convex approximations with the 0.001 / 1.001 split and raa0 / box
+ * regularisation; the dual in the multiplier solved by doubling then
+ * `bisect_iters` bisection steps. */
+typedef struct {
+    double xmin, xmax, move, asy_init, asy_decr, asy_incr, albefa, raa0;
+    int32_t bisect_iters;
+    int32_t reserved;
+} fem_mma_opts;
+int fem_mma_default_opts(fem_mma_opts *opts);
+
+/* One MMA iteration for min f0 s.t. f1 <= 0: x, xold1, xold2 (iterates k, k-1, k-2),
+ * df0, df1 (gradients at x) [n] FP64 device; f1 the constraint value at x (host);
+ * low, upp [n] device in/out (asymptotes; read only from iteration 2 on); xnew [n]
+ * device out; *lambda_out (host, may be NULL) the constraint multiplier.  `iter` is
+ * the 0-based iteration count.  Current device; blocks. */
+int fem_mma_update(int64_t n, int32_t iter, const double *x, const double *xold1, const double *xold2,
+                   const double *df0, double f1, const double *df1, double *low, double *upp, double *xnew,
+                   double *lambda_out, const fem_mma_opts *opts, void *workspace, size_t workspace_bytes,
+                   void *stream);
 
 #ifdef __cplusplus
 }

@@ -1,4 +1,5 @@
 // C ABI of libfem: argument checks, handle lifetime, error translation.
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -48,6 +49,7 @@ void validate_opts(const fem_solve_opts *o) {
     require(o->newton_rtol >= 0.0 && o->newton_atol >= 0.0 && o->adjoint_rtol >= 0.0, "opts tolerances");
     require(o->adjoint_max_refine >= 1, "opts.adjoint_max_refine must be >= 1");
     require(o->newton_fixed_its >= 0, "opts.newton_fixed_its must be >= 0");
+    require(o->precond == FEM_PRECOND_JACOBI || o->precond == FEM_PRECOND_BLOCK_JACOBI, "opts.precond");
 }
 
 void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, size_t bytes) {
@@ -80,6 +82,7 @@ int fem_default_opts(fem_solve_opts *o) {
         o->adjoint_max_refine = 20;
         o->profile_spmv = 0;
         o->newton_fixed_its = 0;
+        o->precond = FEM_PRECOND_JACOBI;
     });
 }
 
@@ -147,6 +150,7 @@ void fem_destroy(fem_handle *h) {
     (void)hipSetDevice(h->device);
     for (auto &e : h->events) (void)hipEventDestroy(e);
     for (void *p : h->allocations) (void)hipFree(p);
+    for (void *p : h->filter.allocations) (void)hipFree(p);
     if (h->host_status) (void)hipHostFree(h->host_status);
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);
     if (h->host_kry) (void)hipHostFree(h->host_kry);
@@ -208,9 +212,10 @@ int fem_assemble(fem_handle *h, const double *u, const double *theta, double *re
         if (residual) fem::launch_residual(h, u, theta, 1.0, rscr, residual, s);
         if (values) {
             if (values_dtype == FEM_F32)
-                fem::launch_tangent<float>(h, u, theta, static_cast<float *>(ke), static_cast<float *>(values), s, ly);
+                fem::launch_tangent<float>(h, u, theta, static_cast<float *>(ke), static_cast<float *>(values), nullptr, s,
+                                           ly);
             else
-                fem::launch_tangent<double>(h, u, theta, static_cast<double *>(ke), static_cast<double *>(values), s,
+                fem::launch_tangent<double>(h, u, theta, static_cast<double *>(ke), static_cast<double *>(values), nullptr, s,
                                             ly);
         }
         fem::check_status(h, s);
@@ -287,6 +292,105 @@ int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const d
         bind_device(h);
         fem::adjoint_vjp(h, u, theta, dJdu, vjp_theta, lambda_out, *opts, stats, workspace, workspace_bytes,
                          as_stream(stream));
+    });
+}
+
+int fem_param_vjp(fem_handle *h, const double *u, const double *theta, const double *lambda, double *vjp_theta,
+                  void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        if (h->g.Ne == 0) return;
+        require(u && theta && lambda && vjp_theta, "u, theta, lambda and vjp_theta must be non-NULL");
+        bind_device(h);
+        fem::reset_status(h, as_stream(stream));
+        fem::launch_vjp(h, u, theta, lambda, vjp_theta, as_stream(stream));
+        fem::check_status(h, as_stream(stream));
+    });
+}
+
+int fem_element_volumes(fem_handle *h, double *volumes, int32_t normalized, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        if (h->g.Ne == 0) return;
+        require(volumes != nullptr, "volumes must be non-NULL");
+        bind_device(h);
+        fem::element_volumes(h, volumes, normalized != 0, as_stream(stream));
+    });
+}
+
+int fem_filter_setup(fem_handle *h, double rmin) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        require(rmin > 0.0 && std::isfinite(rmin), "rmin must be positive");
+        bind_device(h);
+        fem::filter_setup(h, rmin);
+    });
+}
+
+int fem_filter_apply(fem_handle *h, int32_t mode, const double *theta, const double *x, double *out, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        require(mode == FEM_FILTER_DENSITY || mode == FEM_FILTER_SENSITIVITY, "mode");
+        require(h->filter.ready, "fem_filter_setup has not been called");
+        if (h->g.Ne == 0) return;
+        require(x && out, "x and out must be non-NULL");
+        require(x != out, "x and out must be distinct buffers");
+        require(mode == FEM_FILTER_DENSITY || theta != nullptr, "the sensitivity filter needs theta");
+        bind_device(h);
+        fem::filter_apply(h, mode, theta, x, out, as_stream(stream));
+    });
+}
+
+size_t fem_vector_workspace_bytes(int64_t n) { return fem::vector_workspace_bytes(n < 0 ? 0 : n); }
+
+int fem_dot(const double *a, const double *b, int64_t n, double *result, void *workspace, size_t workspace_bytes,
+            void *stream) {
+    return guarded([&] {
+        require(result != nullptr, "result is NULL");
+        require(n >= 0, "n must be >= 0");
+        *result = 0.0;
+        if (n == 0) return;
+        require(a && b, "a and b must be non-NULL");
+        require(workspace && workspace_bytes >= fem::vector_workspace_bytes(n), "workspace too small");
+        *result = fem::dot(a, b, n, workspace, as_stream(stream));
+    });
+}
+
+int fem_mma_default_opts(fem_mma_opts *o) {
+    return guarded([&] {
+        require(o != nullptr, "opts is NULL");
+        std::memset(o, 0, sizeof(*o));
+        o->xmin = 0.0;
+        o->xmax = 1.0;
+        o->move = 0.5;
+        o->asy_init = 0.5;
+        o->asy_decr = 0.7;
+        o->asy_incr = 1.2;
+        o->albefa = 0.1;
+        o->raa0 = 1e-5;
+        o->bisect_iters = 100;
+    });
+}
+
+int fem_mma_update(int64_t n, int32_t iter, const double *x, const double *xold1, const double *xold2,
+                   const double *df0, double f1, const double *df1, double *low, double *upp, double *xnew,
+                   double *lambda_out, const fem_mma_opts *opts, void *workspace, size_t workspace_bytes,
+                   void *stream) {
+    return guarded([&] {
+        require(opts != nullptr, "opts is NULL");
+        require(n >= 0 && iter >= 0, "n and iter must be >= 0");
+        require(opts->xmax > opts->xmin && opts->move > 0.0 && opts->asy_init > 0.0 && opts->asy_decr > 0.0 &&
+                    opts->asy_incr > 0.0 && opts->albefa > 0.0 && opts->albefa < 1.0 && opts->raa0 >= 0.0 &&
+                    opts->bisect_iters >= 0,
+                "mma opts");
+        require(std::isfinite(f1), "f1 is not finite");
+        if (lambda_out) *lambda_out = 0.0;
+        if (n == 0) return;
+        require(x && xold1 && xold2 && df0 && df1 && low && upp && xnew, "vector arguments must be non-NULL");
+        require(workspace && workspace_bytes >= fem::vector_workspace_bytes(n), "workspace too small");
+        const double lam = fem::mma_update(n, iter, x, xold1, xold2, df0, f1, df1, low, upp, xnew, *opts, workspace,
+                                           as_stream(stream));
+        if (lambda_out) *lambda_out = lam;
     });
 }
 

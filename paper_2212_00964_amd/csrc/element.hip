@@ -15,6 +15,8 @@
 //
 // Paper: element residual R_e and K_e = dr_e/dU_e (Sec. 2.2), constitutive laws
 // (Sec. 2.3, Eq. (linear_elasticity), Eq. (neo-hookean)), assembly (Alg. 1).
+#include <algorithm>
+
 #include "internal.h"
 #include "lanes.h"
 
@@ -476,6 +478,166 @@ __global__ __launch_bounds__(256) void k_gather_values(int64_t nnzb, const int64
     if (bad) atomicOr(status, ST_NAN);
 }
 
+// Inverse of an ND x ND block (FP64 cofactors), written row-major to out; false when
+// the block is singular or not finite.
+template <int ND, typename T>
+__device__ __forceinline__ bool invert_block(const double B[ND][ND], T *out) {
+    if constexpr (ND == 1) {
+        out[0] = T(1.0 / B[0][0]);
+        return B[0][0] != 0.0 && isfinite(B[0][0]);
+    } else {
+        const double d = det3(B);
+        double C[3][3];
+        inv_transpose3(B, d, C);  // C = B^{-T}
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[i * 3 + c] = T(C[c][i]);
+        return d != 0.0 && isfinite(d);
+    }
+}
+
+// Block-Jacobi inverses read from assembled values (used when the node-centric gather
+// does not apply): one thread per node.
+template <int ND, int LAYOUT, typename T>
+__global__ __launch_bounds__(256) void k_extract_binv(int64_t Nn, const int64_t *__restrict__ node_ptr,
+                                                      const int32_t *__restrict__ bdiag,
+                                                      const int64_t *__restrict__ row_ptr,
+                                                      const int64_t *__restrict__ up_base,
+                                                      const T *__restrict__ values, T *__restrict__ binv,
+                                                      int *status) {
+    const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= Nn) return;
+    double B[ND][ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+        for (int c = 0; c < ND; ++c)
+            B[i][c] = (LAYOUT == LAYOUT_SYM)
+                          ? double(values[int64_t(ND) * ND * up_base[n] + i * ND + c])
+                          : double(values[row_ptr[ND * n + i] + ND * (bdiag[n] - node_ptr[n]) + c]);
+    if (!invert_block<ND>(B, binv + int64_t(ND) * ND * n)) atomicOr(status, ST_NAN);
+}
+
+// Node-centric gather (one wavefront per node, for node degrees up to
+// kGatherMaxDeg): the node's element row blocks are one contiguous run of slots
+// ne_ptr[n] .. ne_ptr[n+1]-1 (element ascending); each slot's 8 column blocks are
+// added into an LDS image of the node's rows at the positions tgt gives, one slot at
+// a time (so every entry sums its contributions in element order, and no two lanes
+// touch the same entry in a step).  The rows are then written once, coalesced, with
+// the symmetric Dirichlet elimination applied, and the Jacobi inverse diagonal of the
+// node is taken from the same image.
+constexpr int kGatherMaxDeg = 32;
+constexpr int kGatherSlots = 8;  // slots preloaded per pass
+
+template <int ND, int LAYOUT, typename T>
+__global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *__restrict__ node_ptr,
+                                                     const int32_t *__restrict__ node_nb,
+                                                     const int64_t *__restrict__ ne_ptr,
+                                                     const uint8_t *__restrict__ tgt,
+                                                     const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ bdiag,
+                                                     const int64_t *__restrict__ up_base,
+                                                     const uint8_t *__restrict__ mask, const T *__restrict__ ke,
+                                                     T *__restrict__ values, T *__restrict__ dinv, int bj,
+                                                     int *status) {
+    constexpr int BS = ND * ND;
+    constexpr int W = 64;
+    constexpr int PER = (8 * BS + W - 1) / W;  // values of one slot per lane
+    __shared__ T img[256 / W][kGatherMaxDeg * BS];
+    __shared__ uint8_t nbm[256 / W][kGatherMaxDeg];  // Dirichlet bits of each neighbour's dofs
+    // wavefront index made explicitly uniform, so node and slot indices live in scalar
+    // registers and their loads go through the scalar cache
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W), lane = threadIdx.x % W;
+    T *a = img[wave];
+    // Each wavefront walks nodes with a grid stride (a few resident blocks per CU;
+    // one short-lived workgroup per node would be bound by the dispatch rate).  The
+    // loop trip count is uniform per wavefront and the kernel has no block barriers.
+    for (int64_t n = int64_t(blockIdx.x) * (256 / W) + wave; n < Nn; n += int64_t(gridDim.x) * (256 / W)) {
+        const int64_t nb0 = node_ptr[n];
+        const int deg = int(node_ptr[n + 1] - nb0);
+        // Dirichlet bits of the node's own dofs and of its neighbours', fetched up front so
+        // their latency overlaps the value loads
+        int rowbits = 0;
+        if (mask)
+#pragma unroll
+            for (int c = 0; c < ND; ++c) rowbits |= int(mask[ND * n + c] != 0) << c;
+        if (lane < deg) {
+            int bits = 0;
+            if (mask) {
+                const int64_t m = node_nb[nb0 + lane];
+#pragma unroll
+                for (int c = 0; c < ND; ++c) bits |= int(mask[ND * m + c] != 0) << c;
+            }
+            nbm[wave][lane] = uint8_t(bits);
+        }
+        for (int l = lane; l < deg * BS; l += W) a[l] = T(0);
+        const int64_t k1 = ne_ptr[n + 1];
+        for (int64_t k0 = ne_ptr[n]; k0 < k1; k0 += kGatherSlots) {
+            T val[kGatherSlots][PER];
+            int pos[kGatherSlots][PER];
+#pragma unroll
+            for (int kk = 0; kk < kGatherSlots; ++kk) {
+                // the slot index is uniform across the wavefront, so its 8 targets come in
+                // one scalar load; the value loads are unconditional (clamped indices) so
+                // no load sits behind a branch that would wait for everything in flight
+                const bool slot_ok = k0 + kk < k1;
+                const int64_t k = slot_ok ? k0 + kk : k0;
+                const uint64_t tw = *reinterpret_cast<const uint64_t *>(tgt + k * 8);
+#pragma unroll
+                for (int t = 0; t < PER; ++t) {
+                    const int l = lane + W * t;
+                    const bool ok = slot_ok && l < 8 * BS;
+                    const int lc = l < 8 * BS ? l : 0;
+                    const int b = lc / BS;
+                    val[kk][t] = ke[(k * 8) * BS + lc];
+                    const int j = int((tw >> (8 * b)) & 0xff);
+                    pos[kk][t] = ok ? j * BS + (lc - b * BS) : -1;
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < kGatherSlots; ++kk)
+#pragma unroll
+                for (int t = 0; t < PER; ++t)
+                    if (pos[kk][t] >= 0) a[pos[kk][t]] += val[kk][t];
+        }
+        // rows of the node, CSR (or upper blocks only), with the Dirichlet elimination
+        const int jd = int(bdiag[n] - nb0);
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+            const int64_t rbase = (LAYOUT == LAYOUT_SYM) ? 0 : row_ptr[ND * n + i];
+            const bool rm = (rowbits >> i) & 1;
+            for (int r = lane; r < ND * deg; r += W) {
+                const int j = r / ND, c = r - j * ND;
+                T v = a[j * BS + i * ND + c];
+                if (rm || ((nbm[wave][j] >> c) & 1)) v = (j == jd && c == i) ? T(1) : T(0);
+                bad |= !isfinite(v);
+                if (LAYOUT == LAYOUT_SYM) {
+                    if (j >= jd) values[int64_t(BS) * (up_base[n] + j - jd) + i * ND + c] = v;
+                } else {
+                    values[rbase + r] = v;
+                }
+            }
+        }
+        if (dinv && !bj && lane < ND) {
+            T v = ((rowbits >> lane) & 1) ? T(1) : a[jd * BS + lane * ND + lane];
+            bad |= !(v != T(0)) || !isfinite(v);
+            dinv[ND * n + lane] = T(1) / v;
+        }
+        if (dinv && bj && lane == 0) {
+            double B[ND][ND];
+#pragma unroll
+            for (int i = 0; i < ND; ++i)
+#pragma unroll
+                for (int c = 0; c < ND; ++c)
+                    B[i][c] = (((rowbits >> i) | (rowbits >> c)) & 1) ? (i == c ? 1.0 : 0.0) : double(a[jd * BS + i * ND + c]);
+            bad |= !invert_block<ND>(B, dinv + int64_t(BS) * n);
+        }
+        if (bad) atomicOr(status, ST_NAN);
+    }
+}
+
 template <int ND, int LAYOUT, typename T>
 __global__ __launch_bounds__(256) void k_extract_dinv(int64_t N, const int64_t *__restrict__ node_ptr,
                                                       const int32_t *__restrict__ bdiag,
@@ -494,6 +656,11 @@ __global__ __launch_bounds__(256) void k_extract_dinv(int64_t N, const int64_t *
 }
 
 inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads - 1) / threads); }
+
+// Resident grid of the node-centric gather: 8 blocks of 4 wavefronts per CU.
+inline unsigned gather_grid(const fem_handle *h) {
+    return unsigned(std::min<int64_t>(int64_t(8) * h->num_cus, (h->g.Nn + 3) / 4));
+}
 
 }  // namespace
 
@@ -566,24 +733,55 @@ void launch_vjp(const fem_handle *h, const double *u, const double *theta, const
 }
 
 template <typename T>
-void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke, T *values, hipStream_t s,
-                    int layout) {
+void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke, T *values, T *dinv,
+                    hipStream_t s, int layout, int precond) {
+    const int bj = precond == FEM_PRECOND_BLOCK_JACOBI;
     const Graph &g = h->g;
     if (g.Ne == 0) return;
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    const bool node_gather = g.tgt != nullptr && g.max_deg <= kGatherMaxDeg;
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_tangent<MODEL, ND, T>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
                            h->m.conn, g.kpos, h->mat, theta, u, ke, h->status);
-        if (layout == LAYOUT_SYM)
-            hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_SYM, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s,
-                               g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, g.bdiag,
-                               g.up_base, h->m.mask, ke, values, h->status);
-        else
-            hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_CSR, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256), 0, s,
-                               g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr, g.bdiag,
-                               g.up_base, h->m.mask, ke, values, h->status);
+        if (node_gather) {
+            if (layout == LAYOUT_SYM)
+                hipLaunchKernelGGL((k_gather_node<ND, LAYOUT_SYM, T>), dim3(gather_grid(h)), dim3(256), 0, s,
+                                   g.Nn, g.node_ptr, g.node_nb, g.ne_ptr, g.tgt, g.row_ptr, g.bdiag, g.up_base,
+                                   h->m.mask, ke, values, dinv, bj, h->status);
+            else
+                hipLaunchKernelGGL((k_gather_node<ND, LAYOUT_CSR, T>), dim3(gather_grid(h)), dim3(256), 0, s,
+                                   g.Nn, g.node_ptr, g.node_nb, g.ne_ptr, g.tgt, g.row_ptr, g.bdiag, g.up_base,
+                                   h->m.mask, ke, values, dinv, bj, h->status);
+        } else {
+            if (layout == LAYOUT_SYM)
+                hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_SYM, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256),
+                                   0, s, g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr,
+                                   g.bdiag, g.up_base, h->m.mask, ke, values, h->status);
+            else
+                hipLaunchKernelGGL((k_gather_values<ND, LAYOUT_CSR, T>), dim3(grid_for(g.nnzb * ND, 256)), dim3(256),
+                                   0, s, g.nnzb, g.node_ptr, g.node_nb, g.blk_row, g.blk_ptr, g.blk_src, g.row_ptr,
+                                   g.bdiag, g.up_base, h->m.mask, ke, values, h->status);
+        }
     });
     FEM_HIP(hipGetLastError());
+    if (dinv && !node_gather) {
+        if (!bj) {
+            launch_extract_dinv<T>(h, values, dinv, s, layout);
+        } else {
+#define FEM_BINV(ND, LY)                                                                                           \
+    hipLaunchKernelGGL((k_extract_binv<ND, LY, T>), dim3(grid_for(g.Nn, 256)), dim3(256), 0, s, g.Nn, g.node_ptr, \
+                       g.bdiag, g.row_ptr, g.up_base, values, dinv, h->status)
+            if (g.nd == 1) {
+                if (layout == LAYOUT_SYM) FEM_BINV(1, LAYOUT_SYM);
+                else FEM_BINV(1, LAYOUT_CSR);
+            } else {
+                if (layout == LAYOUT_SYM) FEM_BINV(3, LAYOUT_SYM);
+                else FEM_BINV(3, LAYOUT_CSR);
+            }
+#undef FEM_BINV
+            FEM_HIP(hipGetLastError());
+        }
+    }
 }
 
 template <typename T>
@@ -604,10 +802,10 @@ void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStrea
     FEM_HIP(hipGetLastError());
 }
 
-template void launch_tangent<float>(const fem_handle *, const double *, const double *, float *, float *, hipStream_t,
-                                    int);
+template void launch_tangent<float>(const fem_handle *, const double *, const double *, float *, float *, float *,
+                                    hipStream_t, int, int);
 template void launch_tangent<double>(const fem_handle *, const double *, const double *, double *, double *,
-                                     hipStream_t, int);
+                                     double *, hipStream_t, int, int);
 template void launch_extract_dinv<float>(const fem_handle *, const float *, float *, hipStream_t, int);
 template void launch_extract_dinv<double>(const fem_handle *, const double *, double *, hipStream_t, int);
 

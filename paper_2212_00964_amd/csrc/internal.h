@@ -70,6 +70,9 @@ struct Graph {
                                   //        (node n owns slots ne_ptr[n] .. ne_ptr[n+1]-1,
                                   //        element ascending)
     int32_t *bslot = nullptr;     // [Ne*64] block of local pair (a, b) of element e
+    uint8_t *tgt = nullptr;       // [Ne*64] for slot k and column block b: the block's position
+                                  //         in the row node's neighbour list (max_deg <= 255)
+    int max_deg = 0;              // largest node degree of the node graph
     int64_t *row_ptr = nullptr;   // [N+1] scalar CSR row starts
     // Symmetric block layout: only blocks (n, m) with m >= n are stored, block-major
     // (nd x nd, row-major), in CSR order of the node graph.
@@ -88,6 +91,17 @@ struct DeviceMesh {
     std::vector<uint8_t> host_mask;
 };
 
+// Convolution filter over element centroids (CSR over elements).
+struct Filter {
+    int64_t *ptr = nullptr;   // [Ne+1]
+    int32_t *idx = nullptr;   // neighbour elements, ascending
+    double *w = nullptr;      // weights rmin - distance
+    double *wsum = nullptr;   // [Ne] row sums
+    int64_t nnz = 0;
+    bool ready = false;
+    std::vector<void *> allocations;
+};
+
 }  // namespace fem
 
 struct fem_handle {
@@ -103,6 +117,8 @@ struct fem_handle {
     int spmv_group = 16;                      // SpMV tuning knob (nodes in flight per lane group)
     int num_cus = 256;                        // compute units of the device
     std::vector<void *> allocations;          // device allocations owned by the handle
+    fem::Filter filter;                       // fem_filter_setup (owns its allocations)
+    double *red_partials = nullptr;           // reduction partials of fem_element_volumes (lazy)
 };
 
 namespace fem {
@@ -118,10 +134,13 @@ void launch_residual(const fem_handle *h, const double *u, const double *theta, 
                      double *r_scratch, double *r_out, hipStream_t s);
 void launch_apply_tangent(const fem_handle *h, const double *u, const double *theta, const double *v,
                           double *y_scratch, double *y_out, hipStream_t s);
-// ke_scratch: [Ne*64*nd*nd] of the value type; values [nnz].
+// ke_scratch: [Ne*64*nd*nd] of the value type; values [nnz] (or the symmetric block
+// layout); when dinv is not null it receives the preconditioner: the inverse diagonal
+// [N] (FEM_PRECOND_JACOBI) or the inverse node blocks [Nn*nd*nd], row-major
+// (FEM_PRECOND_BLOCK_JACOBI).
 template <typename T>
-void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke_scratch, T *values,
-                    hipStream_t s, int layout = LAYOUT_CSR);
+void launch_tangent(const fem_handle *h, const double *u, const double *theta, T *ke_scratch, T *values, T *dinv,
+                    hipStream_t s, int layout = LAYOUT_CSR, int precond = FEM_PRECOND_JACOBI);
 // y = (K(u) v) on free dofs with v used on every dof (Dirichlet lifting), 0 on Dirichlet dofs.
 void launch_lift(const fem_handle *h, const double *u, const double *theta, const double *v, double *scratch,
                  double *y, hipStream_t s);
@@ -147,7 +166,9 @@ template <typename T>
 struct KrylovVecs {
     const T *A;  // values of the operator
     int layout;  // LAYOUT_CSR or LAYOUT_SYM
-    T *x, *r, *rh, *p, *v, *s, *t, *ph, *sh, *dinv;
+    T *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;
+    T *dinv;     // preconditioner: inverse diagonal [N] or inverse node blocks [Nn*nd*nd]
+    int bj;      // 1: dinv holds node blocks (block Jacobi)
     double *partials;   // per-block partial sums written by one kernel ...
     double *partials2;  // ... and by the next one (the two alternate)
     KrylovScalars *sc;
@@ -162,6 +183,16 @@ void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double
 // CG iteration number `it` (0-based within this solve).
 template <typename T>
 void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev);
+
+// SIMP optimisation pieces (topopt.hip).
+size_t vector_workspace_bytes(int64_t n);
+void element_volumes(fem_handle *h, double *vol, bool normalized, hipStream_t s);
+void filter_setup(fem_handle *h, double rmin);
+void filter_apply(const fem_handle *h, int mode, const double *theta, const double *x, double *out, hipStream_t s);
+double dot(const double *a, const double *b, int64_t n, void *ws, hipStream_t s);
+double mma_update(int64_t n, int iter, const double *x, const double *xold1, const double *xold2, const double *df0,
+                  double f1, const double *df1, double *low, double *upp, double *xnew, const fem_mma_opts &o,
+                  void *ws, hipStream_t s);
 
 // Vector helpers.
 void launch_norm2_free(const fem_handle *h, const double *r, double *partials, double *out, hipStream_t s);

@@ -584,6 +584,137 @@ __global__ __launch_bounds__(kThreads) void k_cg_p_fused(int64_t N, const T *__r
         p[i] = z[i] + bt * p[i];
 }
 
+// ------------------------------------------------------------------ block Jacobi variants
+// The same vector kernels with the node-block preconditioner: one thread per node,
+// z_n = M_n r_n with M_n the inverse of node n's ND x ND diagonal block (row-major).
+template <int ND, typename T>
+__device__ __forceinline__ void node_block_apply(const T *__restrict__ M, int64_t n, const T r[ND], T z[ND]) {
+    const T *m = M + int64_t(ND) * ND * n;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+        T a = T(0);
+#pragma unroll
+        for (int c = 0; c < ND; ++c) a += m[i * ND + c] * r[c];
+        z[i] = a;
+    }
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(kThreads) void k_kry_init_bj(int64_t Nn, int cg, const T *__restrict__ b,
+                                                          T *__restrict__ x, T *__restrict__ r, T *__restrict__ rh,
+                                                          T *__restrict__ p, T *__restrict__ v,
+                                                          const T *__restrict__ M, double *partials) {
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < Nn; n += int64_t(gridDim.x) * kThreads) {
+        T bi[ND], zi[ND];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) bi[c] = b[ND * n + c];
+        if (cg) node_block_apply<ND>(M, n, bi, zi);
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+            const int64_t i = ND * n + c;
+            x[i] = T(0);
+            r[i] = bi[c];
+            if (cg) {
+                rh[i] = zi[c];
+                p[i] = zi[c];
+                d0 += double(bi[c]) * double(zi[c]);
+            } else {
+                rh[i] = bi[c];
+                p[i] = T(0);
+                v[i] = T(0);
+                d0 += double(bi[c]) * double(bi[c]);
+            }
+            d1 += double(bi[c]) * double(bi[c]);
+        }
+    }
+    double vv[2] = {d0, d1};
+    block_store_partials<2>(vv, partials);
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_xr_fused_bj(int64_t Nn, T *__restrict__ x, T *__restrict__ r,
+                                                             T *__restrict__ z, const T *__restrict__ p,
+                                                             const T *__restrict__ q, const T *__restrict__ M,
+                                                             const double *__restrict__ pq_partials, int pq_count,
+                                                             double *partials, KrylovScalars *sc, int it) {
+    if (stopped(sc)) return;
+    double pq[1];
+    sum_partials<1>(pq_partials, pq_count, pq);
+    if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->breakdown = 1;
+        return;
+    }
+    const double alpha = sc->rho_pp[it & 1] / pq[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
+    const T al = T(alpha);
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < Nn; n += int64_t(gridDim.x) * kThreads) {
+        T ri[ND], zi[ND];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+            const int64_t i = ND * n + c;
+            x[i] += al * p[i];
+            ri[c] = r[i] - al * q[i];
+            r[i] = ri[c];
+        }
+        node_block_apply<ND>(M, n, ri, zi);
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+            z[ND * n + c] = zi[c];
+            d0 += double(ri[c]) * double(zi[c]);
+            d1 += double(ri[c]) * double(ri[c]);
+        }
+    }
+    double v[2] = {d0, d1};
+    block_store_partials<2>(v, partials);
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_p_bj(int64_t Nn, const T *__restrict__ r, T *__restrict__ p,
+                                                        const T *__restrict__ v, T *__restrict__ ph,
+                                                        T *__restrict__ rh, const T *__restrict__ M,
+                                                        const KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const bool restart = sc->restart_at == sc->its;
+    const double beta = (sc->its == 0 || restart) ? 0.0 : (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
+    const T bt = T(beta), om = T(sc->omega);
+    for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < Nn; n += int64_t(gridDim.x) * kThreads) {
+        T pi[ND], zi[ND];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+            const int64_t i = ND * n + c;
+            const T ri = r[i];
+            pi[c] = restart ? ri : ri + bt * (p[i] - om * v[i]);
+            p[i] = pi[c];
+            if (restart) rh[i] = ri;
+        }
+        node_block_apply<ND>(M, n, pi, zi);
+#pragma unroll
+        for (int c = 0; c < ND; ++c) ph[ND * n + c] = zi[c];
+    }
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_s_bj(int64_t Nn, const T *__restrict__ r, const T *__restrict__ v,
+                                                        T *__restrict__ s, T *__restrict__ sh,
+                                                        const T *__restrict__ M, const KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    const T al = T(sc->alpha);
+    for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < Nn; n += int64_t(gridDim.x) * kThreads) {
+        T si[ND], zi[ND];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+            const int64_t i = ND * n + c;
+            si[c] = r[i] - al * v[i];
+            s[i] = si[c];
+        }
+        node_block_apply<ND>(M, n, si, zi);
+#pragma unroll
+        for (int c = 0; c < ND; ++c) sh[ND * n + c] = zi[c];
+    }
+}
+
 // Krylov start with x0 = 0: r = rh = b, p = v = 0 (BiCGSTAB) or r = b, z = Dinv b,
 // p = z (CG); reduces |b|^2 and the first rho.
 template <typename T>
@@ -838,8 +969,17 @@ template void launch_spmv_sym<double>(const fem_handle *, const double *, const 
 
 template <typename T>
 void kry_bicg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s) {
-    hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 0, b, k.x, k.r, k.rh, k.p,
-                       k.v, k.dinv, k.partials, k.sc, rtol);
+    if (k.bj) {
+        if (h->g.nd == 1)
+            hipLaunchKernelGGL((k_kry_init_bj<1, T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.Nn, 0, b, k.x,
+                               k.r, k.rh, k.p, k.v, k.dinv, k.partials);
+        else
+            hipLaunchKernelGGL((k_kry_init_bj<3, T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.Nn, 0, b, k.x,
+                               k.r, k.rh, k.p, k.v, k.dinv, k.partials);
+    } else {
+        hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 0, b, k.x, k.r, k.rh,
+                           k.p, k.v, k.dinv, k.partials, k.sc, rtol);
+    }
     hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kThreads), 0, s, krylov_grid(h), k.partials, k.sc, rtol);
     FEM_HIP(hipGetLastError());
 }
@@ -847,8 +987,17 @@ void kry_bicg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, doub
 template <typename T>
 void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s) {
     // CG keeps z in the slot of rh
-    hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 1, b, k.x, k.r, k.rh, k.p,
-                       k.v, k.dinv, k.partials, k.sc, rtol);
+    if (k.bj) {
+        if (h->g.nd == 1)
+            hipLaunchKernelGGL((k_kry_init_bj<1, T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.Nn, 1, b, k.x,
+                               k.r, k.rh, k.p, k.v, k.dinv, k.partials);
+        else
+            hipLaunchKernelGGL((k_kry_init_bj<3, T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.Nn, 1, b, k.x,
+                               k.r, k.rh, k.p, k.v, k.dinv, k.partials);
+    } else {
+        hipLaunchKernelGGL((k_kry_init<T>), dim3(krylov_grid(h)), dim3(kThreads), 0, s, h->g.N, 1, b, k.x, k.r, k.rh,
+                           k.p, k.v, k.dinv, k.partials, k.sc, rtol);
+    }
     hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kThreads), 0, s, krylov_grid(h), k.partials, k.sc, rtol);
     FEM_HIP(hipGetLastError());
 }
@@ -888,11 +1037,16 @@ void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, h
     const int64_t N = h->g.N;
     dim3 grid(krylov_grid(h)), blk(kThreads);
     const T *A = k.A;
-    hipLaunchKernelGGL((k_bicg_p<T>), grid, blk, 0, s, N, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
+    const int64_t Nn = h->g.Nn;
+    if (!k.bj) hipLaunchKernelGGL((k_bicg_p<T>), grid, blk, 0, s, N, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
+    else if (h->g.nd == 1) hipLaunchKernelGGL((k_bicg_p_bj<1, T>), grid, blk, 0, s, Nn, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
+    else hipLaunchKernelGGL((k_bicg_p_bj<3, T>), grid, blk, 0, s, Nn, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
     if (ev) FEM_HIP(hipEventRecord(ev[0], s));
     kry_spmv<T, 1>(h, k.ph, k.v, k.rh, k, 0, A, s);
     if (ev) FEM_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((k_bicg_s<T>), grid, blk, 0, s, N, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
+    if (!k.bj) hipLaunchKernelGGL((k_bicg_s<T>), grid, blk, 0, s, N, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
+    else if (h->g.nd == 1) hipLaunchKernelGGL((k_bicg_s_bj<1, T>), grid, blk, 0, s, Nn, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
+    else hipLaunchKernelGGL((k_bicg_s_bj<3, T>), grid, blk, 0, s, Nn, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
     if (ev) FEM_HIP(hipEventRecord(ev[2], s));
     kry_spmv<T, 2>(h, k.sh, k.t, k.s, k, 0, A, s);
     if (ev) FEM_HIP(hipEventRecord(ev[3], s));
@@ -914,8 +1068,15 @@ void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_
     if (ev) FEM_HIP(hipEventRecord(ev[0], s));
     const int G = kry_spmv<T, 1>(h, k.p, k.v, k.p, k, 1, A, s, false);
     if (ev) FEM_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((k_cg_xr_fused<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.p, k.v, k.dinv, k.partials, G,
-                       k.partials2, k.sc, it);
+    if (!k.bj)
+        hipLaunchKernelGGL((k_cg_xr_fused<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.p, k.v, k.dinv, k.partials, G,
+                           k.partials2, k.sc, it);
+    else if (h->g.nd == 1)
+        hipLaunchKernelGGL((k_cg_xr_fused_bj<1, T>), grid, blk, 0, s, h->g.Nn, k.x, k.r, k.rh, k.p, k.v, k.dinv,
+                           k.partials, G, k.partials2, k.sc, it);
+    else
+        hipLaunchKernelGGL((k_cg_xr_fused_bj<3, T>), grid, blk, 0, s, h->g.Nn, k.x, k.r, k.rh, k.p, k.v, k.dinv,
+                           k.partials, G, k.partials2, k.sc, it);
     hipLaunchKernelGGL((k_cg_p_fused<T>), grid, blk, 0, s, N, k.rh, k.p, k.partials2, int(grid.x), k.sc, it);
     FEM_HIP(hipGetLastError());
 }

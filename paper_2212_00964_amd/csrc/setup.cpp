@@ -125,6 +125,22 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
             for (int a = 0; a < 8; ++a)
                 for (int c = 0; c < 8; ++c) bslot[e * 64 + a * 8 + c] = int32_t(find_block(conn[8 * e + a], conn[8 * e + c]));
     });
+    // node-centric gather: for slot k (element row block) and column block b, the
+    // position of the target block in the row node's neighbour list
+    int64_t max_deg = 0;
+    for (int64_t n = 0; n < Nn; ++n) max_deg = std::max(max_deg, node_ptr[n + 1] - node_ptr[n]);
+    g.max_deg = int(max_deg);
+    std::vector<uint8_t> tgt;
+    if (max_deg <= 255) {
+        tgt.resize(Ne * 64);
+        parallel_for(Ne, [&](int64_t b, int64_t e_end) {
+            for (int64_t e = b; e < e_end; ++e)
+                for (int a = 0; a < 8; ++a) {
+                    const int64_t k = kpos[e * 8 + a], n = conn[8 * e + a];
+                    for (int c = 0; c < 8; ++c) tgt[k * 8 + c] = uint8_t(bslot[e * 64 + a * 8 + c] - node_ptr[n]);
+                }
+        });
+    }
     std::vector<int64_t> blk_ptr(nnzb + 1, 0);
     for (int64_t i = 0; i < Ne * 64; ++i) blk_ptr[bslot[i] + 1]++;
     for (int64_t k = 0; k < nnzb; ++k) blk_ptr[k + 1] += blk_ptr[k];
@@ -167,6 +183,7 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     g.blk_src = upload(h, blk_src);
     g.ne_ptr = upload(h, ne_ptr);
     g.kpos = upload(h, kpos);
+    if (!tgt.empty()) g.tgt = upload(h, tgt);
     g.bslot = upload(h, bslot);
     g.row_ptr = upload(h, row_ptr);
 }

@@ -73,7 +73,8 @@ static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_
     w.values = c.take<T>(kSolverLayout == LAYOUT_SYM ? g.nnzb_up * g.nd * g.nd : g.nnz);
     w.b = c.take<T>(N);
     T *v[10];
-    for (auto &p : v) p = c.take<T>(N);
+    for (int i = 0; i < 9; ++i) v[i] = c.take<T>(N);
+    v[9] = c.take<T>(g.Nn * g.nd * g.nd);  // preconditioner: diagonal or node blocks
     w.x = v[0];
     w.r = v[1];
     w.rh = v[2];
@@ -136,6 +137,7 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
                     static_cast<T *>(w.ph),
                     static_cast<T *>(w.sh),
                     static_cast<T *>(w.dinv),
+                    o.precond == FEM_PRECOND_BLOCK_JACOBI,
                     w.partials,
                     w.partials2,
                     w.sc};
@@ -208,9 +210,10 @@ static double ms_since(clk::time_point t0) {
 }
 
 template <typename T>
-static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const double *theta, hipStream_t s) {
-    launch_tangent<T>(h, u, theta, static_cast<T *>(w.ke), static_cast<T *>(w.values), s, kSolverLayout);
-    launch_extract_dinv<T>(h, static_cast<const T *>(w.values), static_cast<T *>(w.dinv), s, kSolverLayout);
+static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const double *theta, int precond,
+                          hipStream_t s) {
+    launch_tangent<T>(h, u, theta, static_cast<T *>(w.ke), static_cast<T *>(w.values), static_cast<T *>(w.dinv), s,
+                      kSolverLayout, precond);
 }
 
 // One correction: assemble K(u), solve K du = b (b already in w.b), u += du.
@@ -219,7 +222,7 @@ static int correction(fem_handle *h, SolveWork &w, double *u, const double *thet
                       fem_solve_stats *st, double rn, hipStream_t s) {
     const int64_t N = h->g.N;
     auto t0 = clk::now();
-    assemble_into<T>(h, w, u, theta, s);
+    assemble_into<T>(h, w, u, theta, o.precond, s);
     check_status(h, s);
     if (st) st->ms_assemble += ms_since(t0);
     t0 = clk::now();
@@ -323,7 +326,7 @@ static void adjoint_impl(fem_handle *h, const double *u, const double *theta, co
     auto t0 = clk::now();
     // All laws here have major-symmetric tangents and the Dirichlet elimination is
     // symmetric, so (dC/du)^T is the assembled K itself.
-    assemble_into<T>(h, w, u, theta, s);
+    assemble_into<T>(h, w, u, theta, o.precond, s);
     launch_mask_copy(h, dJdu, w.res64, s);  // b = dJ/du with Dirichlet entries 0
     double bn = norm2(h, w.res64, w, s);
     check_status(h, s);

@@ -25,6 +25,8 @@ F32, F64 = 0, 1
 LAYOUT_CSR, LAYOUT_SYM_BLOCK = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 CG, BICGSTAB = 0, 1
+PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1
+FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
 MAX_HIST = 64
 
 
@@ -55,7 +57,7 @@ class SolveOpts(ctypes.Structure):
                 ("newton_atol", ctypes.c_double), ("krylov_rtol", ctypes.c_double),
                 ("krylov_max_it", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("adjoint_rtol", ctypes.c_double), ("adjoint_max_refine", ctypes.c_int32),
-                ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -75,10 +77,19 @@ class SolveStats(ctypes.Structure):
         return d
 
 
+class MmaOpts(ctypes.Structure):
+    _fields_ = [("xmin", ctypes.c_double), ("xmax", ctypes.c_double), ("move", ctypes.c_double),
+                ("asy_init", ctypes.c_double), ("asy_decr", ctypes.c_double), ("asy_incr", ctypes.c_double),
+                ("albefa", ctypes.c_double), ("raa0", ctypes.c_double), ("bisect_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 # Names, in the order the header declares them (checked by the CPU test-suite).
 EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
            "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv",
-           "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp"]
+           "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_param_vjp", "fem_element_volumes",
+           "fem_filter_setup", "fem_filter_apply", "fem_vector_workspace_bytes", "fem_dot", "fem_mma_default_opts",
+           "fem_mma_update"]
 
 _lib = None
 
@@ -111,6 +122,15 @@ def lib():
         "fem_apply_tangent": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "fem_newton_solve": (ctypes.c_int, [vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
         "fem_adjoint_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
+        "fem_param_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "fem_element_volumes": (ctypes.c_int, [vp, vp, i32, vp]),
+        "fem_filter_setup": (ctypes.c_int, [vp, dbl]),
+        "fem_filter_apply": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
+        "fem_vector_workspace_bytes": (sz, [i64]),
+        "fem_dot": (ctypes.c_int, [vp, vp, i64, P(dbl), vp, sz, vp]),
+        "fem_mma_default_opts": (ctypes.c_int, [P(MmaOpts)]),
+        "fem_mma_update": (ctypes.c_int, [i64, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp, P(dbl), P(MmaOpts), vp, sz,
+                                          vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -143,6 +163,46 @@ def default_opts(**kw) -> SolveOpts:
             raise AttributeError(k)
         setattr(o, k, v)
     return o
+
+
+def mma_default_opts(**kw) -> MmaOpts:
+    o = MmaOpts()
+    _check(lib().fem_mma_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _vector_workspace(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(lib().fem_vector_workspace_bytes(n)), 256), dtype=torch.uint8, device=device)
+
+
+def dot(a: torch.Tensor, b: torch.Tensor, workspace: Optional[torch.Tensor] = None) -> float:
+    """Deterministic FP64 dot product of two device vectors (fem_dot)."""
+    if a.dtype != torch.float64 or b.dtype != torch.float64 or a.numel() != b.numel():
+        raise ValueError("dot needs two float64 vectors of equal length")
+    a, b = a.contiguous(), b.contiguous()
+    ws = _vector_workspace(a.numel(), a.device) if workspace is None else workspace
+    out = ctypes.c_double()
+    _check(lib().fem_dot(_ptr(a), _ptr(b), a.numel(), ctypes.byref(out), _ptr(ws), ws.numel(), _stream()))
+    return out.value
+
+
+def mma_update(it: int, x, xold1, xold2, df0, f1: float, df1, low, upp, opts: Optional[MmaOpts] = None,
+               workspace: Optional[torch.Tensor] = None):
+    """One MMA iteration (fem_mma_update).  low/upp are updated in place; returns
+    (xnew, lambda)."""
+    n = x.numel()
+    opts = mma_default_opts() if opts is None else opts
+    ws = _vector_workspace(n, x.device) if workspace is None else workspace
+    xnew = torch.empty_like(x)
+    lam = ctypes.c_double()
+    _check(lib().fem_mma_update(n, it, _ptr(x), _ptr(xold1), _ptr(xold2), _ptr(df0), float(f1), _ptr(df1),
+                                _ptr(low), _ptr(upp), _ptr(xnew), ctypes.byref(lam), ctypes.byref(opts), _ptr(ws),
+                                ws.numel(), _stream()))
+    return xnew, lam.value
 
 
 def _host(a, dt):
@@ -275,6 +335,31 @@ class Problem:
         _check(lib().fem_apply_tangent(self.handle, _ptr(u), _ptr(theta), _ptr(v), _ptr(y), _ptr(ws), ws.numel(),
                                        _stream()))
         return y
+
+    def param_vjp(self, u, lam, theta=None) -> torch.Tensor:
+        """-lambda^T dC/dtheta per element for a given lambda (fem_param_vjp)."""
+        u = self._f64(u, self.n_dofs)
+        lam = self._f64(lam, self.n_dofs)
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        g = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
+        _check(lib().fem_param_vjp(self.handle, _ptr(u), _ptr(theta), _ptr(lam), _ptr(g), _stream()))
+        return g
+
+    def element_volumes(self, normalized: bool = False) -> torch.Tensor:
+        """Element volumes, or with normalized=True the fractions v_e / sum_f v_f."""
+        v = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
+        _check(lib().fem_element_volumes(self.handle, _ptr(v), int(normalized), _stream()))
+        return v
+
+    def filter_setup(self, rmin: float):
+        _check(lib().fem_filter_setup(self.handle, float(rmin)))
+
+    def filter_apply(self, x, mode: int = FILTER_DENSITY, theta=None) -> torch.Tensor:
+        x = self._f64(x, self.n_elems)
+        theta = None if theta is None else self._f64(theta, self.n_elems)
+        out = torch.empty_like(x)
+        _check(lib().fem_filter_apply(self.handle, mode, _ptr(theta), _ptr(x), _ptr(out), _stream()))
+        return out
 
     def opts(self, **kw) -> SolveOpts:
         kw.setdefault("krylov", self.spec.krylov)

@@ -256,6 +256,33 @@ def test_nh_homogeneous_closed_form_on_gpu(precision):
     prob.close()
 
 
+@pytest.mark.parametrize("name", ["cantilever-7x3x5", "nh-9x7x6-5steps", "poisson-8cube"])
+@pytest.mark.parametrize("krylov", [fem.CG, fem.BICGSTAB])
+@pytest.mark.parametrize("precision", [fem.PREC_FP64, fem.PREC_MIXED])
+def test_newton_block_jacobi_matches_oracle(name, krylov, precision):
+    """Node-block Jacobi preconditioner (3x3 inverse per node; plain Jacobi for Poisson):
+    the solution is the oracle's to the same bars as with the point preconditioner."""
+    p, lin = SOLVE_CASES[name]
+    u_ref = orc.newton_solve(p, linear=lin, rtol=1e-13)
+    prob = fem.Problem(p, DEV)
+    fp64 = precision == fem.PREC_FP64
+    u, st = prob.newton_solve(precision=precision, krylov=krylov, precond=fem.PRECOND_BLOCK_JACOBI,
+                              newton_rtol=1e-13 if fp64 else 1e-10, krylov_rtol=1e-8 if fp64 else 1e-5)
+    assert rel(host(u), u_ref) <= (1e-10 if fp64 else 1e-6), st.as_dict()
+    prob.close()
+
+
+def test_block_jacobi_reduces_iterations_and_matches_point_jacobi():
+    p = gen.nh_tensile(12, 10, 8, n_load_steps=2, seed=3, distort_seed=2)
+    prob = fem.Problem(p, DEV)
+    u1, s1 = prob.newton_solve(precision=fem.PREC_FP64, krylov=fem.CG, newton_rtol=1e-12, krylov_rtol=1e-6)
+    u2, s2 = prob.newton_solve(precision=fem.PREC_FP64, krylov=fem.CG, newton_rtol=1e-12, krylov_rtol=1e-6,
+                               precond=fem.PRECOND_BLOCK_JACOBI)
+    assert rel(host(u2), host(u1)) <= 1e-9
+    assert s2.krylov_its_total < s1.krylov_its_total, (s1.krylov_its_total, s2.krylov_its_total)
+    prob.close()
+
+
 # ----------------------------------------------------------------------------- adjoint
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-8), (1, 1e-5)])
@@ -269,6 +296,11 @@ def test_adjoint_matches_oracle(precision, tol):
                                   krylov_rtol=1e-8 if precision == 0 else 1e-5)
     assert rel(host(lam), lam_ref) <= tol, st.as_dict()
     assert rel(host(g), g_ref) <= tol
+    g2, lam2, st2 = prob.adjoint_vjp(u_ref, dJdu, precision=precision, precond=fem.PRECOND_BLOCK_JACOBI,
+                                     adjoint_rtol=1e-11 if precision == 0 else 1e-9,
+                                     krylov_rtol=1e-8 if precision == 0 else 1e-5)
+    assert rel(host(lam2), lam_ref) <= tol, st2.as_dict()
+    assert rel(host(g2), g_ref) <= tol
     prob.close()
 
 
