@@ -276,7 +276,9 @@ int fem_dot(const double *a, const double *b, int64_t n, double *result, void *w
  * and 10 box widths from x; move limits albefa of the distance to the asymptote and
  * `move` * box; convex approximations with the 0.001 / 1.001 split and raa0 / box
  * regularisation; the dual in the multiplier solved by doubling then
- * `bisect_iters` bisection steps. */
+ * `bisect_iters` bisection steps.  When the approximated constraint cannot be met
+ * inside the move limits (the doubling reaches 2^200), the step takes that
+ * multiplier, i.e. the point of the move box that minimises the approximation. */
 typedef struct {
     double xmin, xmax, move, asy_init, asy_decr, asy_incr, albefa, raa0;
     int32_t bisect_iters;

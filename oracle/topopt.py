@@ -20,8 +20,10 @@ detail; the readings taken here (shared by the GPU path) are:
   distance to the asymptote and 0.5 of the box, the convex separable approximations
   with the small regularisation (0.001 / 1.001 weights and 1e-5 / box) of Svanberg's
   later description of the method, and the one-dimensional dual solved by bisection
-  on the multiplier (no artificial variables: a 50 % volume constraint is always
-  feasible inside the box).
+  on the multiplier (no artificial variables).  When the approximated constraint
+  cannot be met inside the move limits even as the multiplier grows (the doubling
+  reaches 2^200), the step takes that multiplier, i.e. the point of the move box that
+  minimises the constraint approximation.
 """
 from __future__ import annotations
 
@@ -35,6 +37,7 @@ GAMMA = 1e-3          # lower bound of theta in the sensitivity filter's denomin
 ASY_INIT, ASY_DECR, ASY_INCR = 0.5, 0.7, 1.2
 ALBEFA, MOVE, RAA0 = 0.1, 0.5, 1e-5
 BISECT_ITERS = 100
+MAX_DOUBLINGS = 200
 
 
 def element_centroids(prob) -> np.ndarray:
@@ -119,15 +122,20 @@ def mma_step(it, x, xold1, xold2, df0, f1, df1, low, upp, xmin=0.0, xmax=1.0):
     if g(0.0) <= 0.0:
         lam = 0.0
     else:
-        while g(lam_hi) > 0.0:
+        doublings = 0
+        while g(lam_hi) > 0.0 and doublings < MAX_DOUBLINGS:
             lam_lo, lam_hi = lam_hi, 2.0 * lam_hi
-        for _ in range(BISECT_ITERS):
-            mid = 0.5 * (lam_lo + lam_hi)
-            if g(mid) > 0.0:
-                lam_lo = mid
-            else:
-                lam_hi = mid
-        lam = 0.5 * (lam_lo + lam_hi)
+            doublings += 1
+        if g(lam_hi) > 0.0:  # not satisfiable inside the move limits
+            lam = lam_hi
+        else:
+            for _ in range(BISECT_ITERS):
+                mid = 0.5 * (lam_lo + lam_hi)
+                if g(mid) > 0.0:
+                    lam_lo = mid
+                else:
+                    lam_hi = mid
+            lam = 0.5 * (lam_lo + lam_hi)
     return x_of(lam), low, upp, lam
 
 

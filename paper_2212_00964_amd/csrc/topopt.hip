@@ -341,20 +341,27 @@ double mma_update(int64_t n, int iter, const double *x, const double *xold1, con
         FEM_HIP(hipGetLastError());
         return r1 + host_sum(partials, pin, s);
     };
+    // Dual in the multiplier: doubling until the approximated constraint is met, then
+    // bisection.  If it cannot be met inside the move limits (2^200 reached), the step
+    // takes that multiplier: the point of the move box minimising the approximation.
+    constexpr int kMaxDoublings = 200;
     double lam = 0.0;
     if (g(0.0) > 0.0) {
         double lo = 0.0, hi = 1.0;
-        for (int k = 0; g(hi) > 0.0; ++k) {
-            if (k > 2000) throw Error(FEM_EMAXITER, "MMA dual: constraint cannot be met inside the move limits");
+        for (int k = 0; k < kMaxDoublings && g(hi) > 0.0; ++k) {
             lo = hi;
             hi *= 2.0;
         }
-        for (int k = 0; k < o.bisect_iters; ++k) {
-            const double mid = 0.5 * (lo + hi);
-            if (g(mid) > 0.0) lo = mid;
-            else hi = mid;
+        if (g(hi) > 0.0) {
+            lam = hi;
+        } else {
+            for (int k = 0; k < o.bisect_iters; ++k) {
+                const double mid = 0.5 * (lo + hi);
+                if (g(mid) > 0.0) lo = mid;
+                else hi = mid;
+            }
+            lam = 0.5 * (lo + hi);
         }
-        lam = 0.5 * (lo + hi);
     }
     hipLaunchKernelGGL(k_mma_final, dim3(grid_for(n)), dim3(kThreads), 0, s, n, lam, low, upp, A, xnew);
     FEM_HIP(hipGetLastError());

@@ -34,7 +34,7 @@ class SimpCompliance:
         self.xold2 = x.clone()
         self.low = torch.zeros_like(self.x)
         self.upp = torch.ones_like(self.x)
-        self.ws = fem._vector_workspace(n, self.x.device)
+        self.ws = fem._vector_workspace(max(n, prob.n_dofs), self.x.device)
         self.it = 0
         self.u = None
         self.compliance: List[float] = []
