@@ -19,6 +19,8 @@
  *   compressible neo-Hookean .................. Sec. 2.3, Eq. (neo-hookean)
  *   Jacobi-preconditioned BiCGSTAB ............ Sec. 5 (conclusions, item 2), van der Vorst 1992
  *   adjoint gradient -lambda^T dC/dtheta ...... Sec. 3, Eq. (adjoint_PDE), Eq. (adjoint_chain_simp)
+ *   perfect J2 plasticity (return map) ........ Sec. 2.3, Eq. (plasticity_strong) and the update
+ *                                               equations that follow it
  *
  * Readings where the paper is silent (HEX8 node order, 2x2x2 Gauss rule,
  * interpolated nodal source, symmetric Dirichlet elimination, CSR layout) are
@@ -32,6 +34,7 @@
 #define ORC_POISSON 0
 #define ORC_ELASTIC 1
 #define ORC_NEOHOOKE 2
+#define ORC_J2 3
 
 #define ORC_OK 0
 #define ORC_EMESH (-4)      /* det(dx/dxi) <= 0 at a Gauss point */
@@ -45,6 +48,7 @@ typedef struct {
     double nu;         /* Poisson ratio (linear elasticity) */
     double bulk_ratio; /* kappa = bulk_ratio * G (neo-Hookean) */
     double simp_p, simp_emin, simp_e0;
+    double yield_stress; /* sigma_yield (J2 plasticity) */
 } orc_material;
 
 /* Reference coordinates of the eight HEX8 nodes (bottom face counter-clockwise, then top). */
@@ -750,5 +754,208 @@ int orc_elements_dense(int64_t n_sel, const int64_t *sel, int ndpn, const double
             if (rc) return rc;
         }
     }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ perfect J2 plasticity
+ * Small-strain perfect J2 plasticity in the form the paper states (Sec. 2.3, the
+ * plasticity paragraph): with the total strain eps^{k-1} and the stress sigma^{k-1}
+ * of the previous load step,
+ *   d_eps = sym(grad u^k) - eps^{k-1}
+ *   sigma_trial = sigma^{k-1} + lambda tr(d_eps) I + 2 mu d_eps
+ *   s = dev(sigma_trial),  |s|_vm = sqrt(3/2 s:s),  f = |s|_vm - sigma_yield
+ *   sigma^k = sigma_trial - (s / |s|_vm) <f>_+
+ * E = mod (per element), nu from the material.  History per Gauss point: 12 values,
+ * eps^{k-1} then sigma^{k-1}, each symmetric tensor as (xx, yy, zz, yz, xz, xy). */
+
+static void sym_from6(const double v[6], double T[3][3]) {
+    T[0][0] = v[0]; T[1][1] = v[1]; T[2][2] = v[2];
+    T[1][2] = T[2][1] = v[3];
+    T[0][2] = T[2][0] = v[4];
+    T[0][1] = T[1][0] = v[5];
+}
+
+static void sym_to6(const double T[3][3], double v[6]) {
+    v[0] = T[0][0]; v[1] = T[1][1]; v[2] = T[2][2];
+    v[3] = T[1][2]; v[4] = T[0][2]; v[5] = T[0][1];
+}
+
+int orc_j2_stress(const orc_material *m, double E, const double Gu[3][3], const double hist[12], double sig[3][3],
+                  int *yielding) {
+    double nu = m->nu;
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E / (2.0 * (1.0 + nu));
+    double ep[3][3], sp[3][3], de[3][3], st[3][3], dev[3][3];
+    sym_from6(hist, ep);
+    sym_from6(hist + 6, sp);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) de[i][j] = 0.5 * (Gu[i][j] + Gu[j][i]) - ep[i][j];
+    double tr = de[0][0] + de[1][1] + de[2][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) st[i][j] = sp[i][j] + 2.0 * mu * de[i][j] + (i == j ? lam * tr : 0.0);
+    double p = (st[0][0] + st[1][1] + st[2][2]) / 3.0, ss = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            dev[i][j] = st[i][j] - (i == j ? p : 0.0);
+            ss += dev[i][j] * dev[i][j];
+        }
+    double svm = sqrt(1.5 * ss), f = svm - m->yield_stress;
+    double ramp = 0.5 * (f + fabs(f));
+    if (yielding) *yielding = f > 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) sig[i][j] = st[i][j] - (ramp > 0.0 ? dev[i][j] / svm * ramp : 0.0);
+    return ORC_OK;
+}
+
+/* d sigma^k / d grad u^k (consistent tangent of the return map above; the paper obtains
+ * it by automatic differentiation).  Elastic: lambda I(x)I + 2 mu I_sym.  Yielding:
+ * kappa I(x)I + 2 mu (sigma_y / |s|_vm) (I_sym - I(x)I / 3 - 3/2 s(x)s / |s|_vm^2) with
+ * kappa = lambda + 2 mu / 3 (the trial deviator s).  Layout A[i][J][k][L]. */
+int orc_j2_tangent(const orc_material *m, double E, const double Gu[3][3], const double hist[12],
+                   double A[3][3][3][3]) {
+    double nu = m->nu;
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E / (2.0 * (1.0 + nu));
+    double ep[3][3], sp[3][3], de[3][3], st[3][3], dev[3][3];
+    sym_from6(hist, ep);
+    sym_from6(hist + 6, sp);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) de[i][j] = 0.5 * (Gu[i][j] + Gu[j][i]) - ep[i][j];
+    double tr = de[0][0] + de[1][1] + de[2][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) st[i][j] = sp[i][j] + 2.0 * mu * de[i][j] + (i == j ? lam * tr : 0.0);
+    double p = (st[0][0] + st[1][1] + st[2][2]) / 3.0, ss = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            dev[i][j] = st[i][j] - (i == j ? p : 0.0);
+            ss += dev[i][j] * dev[i][j];
+        }
+    double svm = sqrt(1.5 * ss);
+    int plastic = svm - m->yield_stress > 0.0;
+    double kappa = lam + 2.0 * mu / 3.0;
+    double mup = plastic ? mu * m->yield_stress / svm : mu;
+    double beta = plastic ? 3.0 * mup / (svm * svm) : 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J)
+            for (int k = 0; k < 3; ++k)
+                for (int L = 0; L < 3; ++L)
+                    A[i][J][k][L] = (kappa - 2.0 * mup / 3.0) * (i == J) * (k == L) +
+                                    mup * ((i == k) * (J == L) + (i == L) * (J == k)) - beta * dev[i][J] * dev[k][L];
+    return ORC_OK;
+}
+
+/* Element residual and tangent of the J2 law (history hist_e[q*12 .. q*12+11] per Gauss
+ * point); Ke may be NULL. */
+static int j2_element(const orc_material *m, double E, const double X[8][3], const double Ue[24],
+                      const double *hist_e, double *re, double *Ke) {
+    memset(re, 0, 24 * sizeof(double));
+    if (Ke) memset(Ke, 0, 24 * 24 * sizeof(double));
+    for (int q = 0; q < 8; ++q) {
+        double xi[3], N[8], gradN[8][3], detJ, Gu[3][3], S[3][3], A[3][3][3][3];
+        orc_gauss_point(q, xi);
+        int rc = orc_geometry(X, xi, N, gradN, &detJ);
+        if (rc) return rc;
+        grad_u(3, Ue, gradN, Gu);
+        orc_j2_stress(m, E, Gu, hist_e + 12 * q, S, NULL);
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (int J = 0; J < 3; ++J) s += S[i][J] * gradN[a][J];
+                re[3 * a + i] += detJ * s;
+            }
+        if (!Ke) continue;
+        orc_j2_tangent(m, E, Gu, hist_e + 12 * q, A);
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i)
+                for (int b = 0; b < 8; ++b)
+                    for (int k = 0; k < 3; ++k) {
+                        double s = 0.0;
+                        for (int J = 0; J < 3; ++J)
+                            for (int L = 0; L < 3; ++L) s += gradN[a][J] * A[i][J][k][L] * gradN[b][L];
+                        Ke[(3 * a + i) * 24 + 3 * b + k] += detJ * s;
+                    }
+    }
+    return ORC_OK;
+}
+
+/* Alg. 1 for the J2 law: residual R_int(u; history) - F and the tangent, with the same
+ * symmetric Dirichlet elimination as orc_assemble.  hist [n_elems * 8 * 12]. */
+int orc_j2_assemble(int64_t n_nodes, int64_t n_elems, const double *coords, const int32_t *conn,
+                    const orc_material *m, const double *theta, const double *hist, const double *u,
+                    const uint8_t *mask, const double *F, const int64_t *row_ptr, const int32_t *col_idx,
+                    const int32_t *slot, double *r, double *values) {
+    int64_t N = n_nodes * 3;
+    if (r)
+        for (int64_t d = 0; d < N; ++d) r[d] = 0.0;
+    if (values) memset(values, 0, (size_t)row_ptr[N] * sizeof(double));
+    double X[8][3], Ue[24], re[24];
+    double *Ke = values ? malloc(24 * 24 * sizeof(double)) : NULL;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        gather_element(coords, conn, e, 3, u, X, Ue);
+        int rc = j2_element(m, orc_modulus(m, theta[e]), X, Ue, hist + 96 * e, re, Ke);
+        if (rc) {
+            free(Ke);
+            return rc;
+        }
+        if (r)
+            for (int p = 0; p < 24; ++p) r[3 * (int64_t)conn[8 * e + p / 3] + p % 3] += re[p];
+        if (values)
+            for (int p = 0; p < 24; ++p)
+                for (int q = 0; q < 24; ++q) values[slot[((int64_t)e * 24 + p) * 24 + q]] += Ke[p * 24 + q];
+    }
+    free(Ke);
+    if (r)
+        for (int64_t d = 0; d < N; ++d) {
+            if (F) r[d] -= F[d];
+            if (mask && mask[d]) r[d] = 0.0;
+        }
+    if (values && mask)
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+                int64_t j = col_idx[k];
+                if (mask[i] || mask[j]) values[k] = (i == j) ? 1.0 : 0.0;
+            }
+    return ORC_OK;
+}
+
+/* New history after a converged load step: eps^k = sym(grad u^k), sigma^k from the
+ * return map, at every Gauss point.  hist_out may alias hist_in. */
+int orc_j2_update_history(int64_t n_elems, const double *coords, const int32_t *conn, const orc_material *m,
+                          const double *theta, const double *u, const double *hist_in, double *hist_out) {
+    double X[8][3], Ue[24];
+    for (int64_t e = 0; e < n_elems; ++e) {
+        gather_element(coords, conn, e, 3, u, X, Ue);
+        double E = orc_modulus(m, theta[e]);
+        for (int q = 0; q < 8; ++q) {
+            double xi[3], N[8], gradN[8][3], detJ, Gu[3][3], S[3][3], eps[3][3];
+            orc_gauss_point(q, xi);
+            int rc = orc_geometry(X, xi, N, gradN, &detJ);
+            if (rc) return rc;
+            grad_u(3, Ue, gradN, Gu);
+            orc_j2_stress(m, E, Gu, hist_in + 96 * e + 12 * q, S, NULL);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) eps[i][j] = 0.5 * (Gu[i][j] + Gu[j][i]);
+            sym_to6(eps, hist_out + 96 * e + 12 * q);
+            sym_to6(S, hist_out + 96 * e + 12 * q + 6);
+        }
+    }
+    return ORC_OK;
+}
+
+/* Volume average of the stress history (xx, yy, zz, yz, xz, xy). */
+int orc_j2_average_stress(int64_t n_elems, const double *coords, const int32_t *conn, const double *hist,
+                          double out[6]) {
+    double X[8][3], vol = 0.0;
+    memset(out, 0, 6 * sizeof(double));
+    for (int64_t e = 0; e < n_elems; ++e) {
+        gather_element(coords, conn, e, 3, NULL, X, NULL);
+        for (int q = 0; q < 8; ++q) {
+            double xi[3], N[8], gradN[8][3], detJ;
+            orc_gauss_point(q, xi);
+            int rc = orc_geometry(X, xi, N, gradN, &detJ);
+            if (rc) return rc;
+            vol += detJ;
+            for (int c = 0; c < 6; ++c) out[c] += detJ * hist[96 * e + 12 * q + 6 + c];
+        }
+    }
+    for (int c = 0; c < 6; ++c) out[c] /= vol;
     return ORC_OK;
 }

@@ -48,7 +48,7 @@ class OracleError(RuntimeError):
 class Material(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("pmap", ctypes.c_int32), ("nu", ctypes.c_double),
                 ("bulk_ratio", ctypes.c_double), ("simp_p", ctypes.c_double), ("simp_emin", ctypes.c_double),
-                ("simp_e0", ctypes.c_double)]
+                ("simp_e0", ctypes.c_double), ("yield_stress", ctypes.c_double)]
 
 
 def _load():
@@ -85,6 +85,12 @@ def _load():
                                 ctypes.POINTER(ctypes.c_double)]),
         "orc_vjp_theta": (_int, [_i64, _int, _dp, _i32p, M, _dp, _dp, _dp, _vp, _dp]),
         "orc_elements_dense": (_int, [_i64, _i64p, _int, _dp, _i32p, M, _dp, _vp, _vp, _vp]),
+        "orc_j2_stress": (_int, [M, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(_int)]),
+        "orc_j2_tangent": (_int, [M, ctypes.c_double, _dp, _dp, _dp]),
+        "orc_j2_assemble": (_int, [_i64, _i64, _dp, _i32p, M, _dp, _dp, _dp, _vp, _vp, _i64p, _i32p, _i32p, _vp,
+                                   _vp]),
+        "orc_j2_update_history": (_int, [_i64, _dp, _i32p, M, _dp, _dp, _dp, _dp]),
+        "orc_j2_average_stress": (_int, [_i64, _dp, _i32p, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -112,7 +118,8 @@ def _c(a, dt):
 
 
 def material(prob) -> Material:
-    return Material(prob.model, prob.pmap, prob.nu, prob.bulk_ratio, prob.simp_p, prob.simp_emin, prob.simp_e0)
+    return Material(prob.model, prob.pmap, prob.nu, prob.bulk_ratio, prob.simp_p, prob.simp_emin, prob.simp_e0,
+                    getattr(prob, "yield_stress", 0.0))
 
 
 # ----------------------------------------------------------------------------- element level

@@ -30,7 +30,7 @@ from typing import Optional
 import numpy as np
 
 # model / parameter-map codes shared by both implementations' interfaces
-POISSON, LINEAR_ELASTIC, NEO_HOOKEAN = 0, 1, 2
+POISSON, LINEAR_ELASTIC, NEO_HOOKEAN, J2_PLASTIC = 0, 1, 2, 3
 THETA_IDENTITY, THETA_SIMP = 0, 1
 CG, BICGSTAB = 0, 1
 
@@ -55,6 +55,7 @@ class Problem:
     simp_p: float = 3.0
     simp_emin: float = 1e-3
     simp_e0: float = 1.0
+    yield_stress: float = 0.0                     # J2 plasticity
     traction_faces: Optional[np.ndarray] = None   # [nf, 2] int32 (element, local face)
     traction: Optional[np.ndarray] = None         # [nf, ndpn] float64
     source_nodal: Optional[np.ndarray] = None     # [Nn*ndpn] float64 nodal source values
@@ -303,12 +304,93 @@ def nh_inverse(nx: int = 200, ny: int = 100, nz: int = 100, L=(2.0, 1.0, 1.0), s
     return p, theta_true
 
 
+def cylinder_mesh(n: int, nz: int, R: float = 5.0, H: float = 10.0):
+    """HEX8 mesh of the cylinder x^2 + y^2 <= R^2, 0 <= z <= H: the structured n x n x nz
+    grid of [-1, 1]^2 x [0, H], its cross-section mapped onto the disk by
+    (x, y) -> R (x sqrt(1 - y^2 / 2), y sqrt(1 - x^2 / 2)) (a smooth map of the square
+    onto the disk; boundary nodes land on the circle)."""
+    coords, conn = box_mesh(n, n, nz, 2.0, 2.0, H)
+    x, y = coords[:, 0] - 1.0, coords[:, 1] - 1.0
+    out = coords.copy()
+    out[:, 0] = R * x * np.sqrt(1.0 - 0.5 * y * y)
+    out[:, 1] = R * y * np.sqrt(1.0 - 0.5 * x * x)
+    return out, conn
+
+
+def j2_cylinder(n: int = 8, nz: int = 16, R: float = 5.0, H: float = 10.0, E: float = 70e3, nu: float = 0.3,
+                yield_stress: float = 250.0, disp: float = 0.1, n_load_steps: int = 10) -> Problem:
+    """Perfect J2 plasticity in uniaxial tension of a cylinder (radius R, height H): bottom
+    face fixed, top face moved by (0, 0, disp); dirichlet_values hold the fully loaded
+    state, reached in n_load_steps (unloading is a second solve back to zero)."""
+    coords, conn = cylinder_mesh(n, nz, R, H)
+    bottom = _on_plane(coords, 2, 0.0, H)
+    top = _on_plane(coords, 2, H, H)
+    vals = np.zeros((coords.shape[0], 3))
+    vals[top, 2] = disp
+    return Problem(
+        name=f"j2-cylinder-{n}x{n}x{nz}", coords=coords, conn=conn, ndpn=3, model=J2_PLASTIC,
+        theta=np.full(conn.shape[0], E), dirichlet_mask=_dof_mask(bottom | top, 3, (0, 1, 2)),
+        dirichlet_values=vals.ravel(), nu=nu, yield_stress=yield_stress, n_load_steps=n_load_steps, krylov=CG,
+        shape=(n, n, nz), lengths=(2.0 * R, 2.0 * R, H))
+
+
+def j2_roller_uniaxial(nx: int, ny: int, nz: int, strain: float = 0.01, E: float = 70e3, nu: float = 0.3,
+                       yield_stress: float = 250.0, n_load_steps: int = 5,
+                       distort_seed: Optional[int] = None) -> Problem:
+    """Unit cube of J2 material on symmetry rollers (u_x=0 on x=0, u_y=0 on y=0, u_z=0
+    on z=0) with u_z = strain on z=1: the exact discrete solution is homogeneous
+    uniaxial stress, sigma_zz following the one-dimensional elastic-perfectly-plastic
+    recursion (a closed-form check)."""
+    coords, conn = box_mesh(nx, ny, nz)
+    if distort_seed is not None:
+        coords = distort(coords, (nx, ny, nz), (1.0, 1.0, 1.0), distort_seed)
+    Nn = coords.shape[0]
+    m = np.zeros((Nn, 3), dtype=np.uint8)
+    m[_on_plane(coords, 0, 0.0, 1.0), 0] = 1
+    m[_on_plane(coords, 1, 0.0, 1.0), 1] = 1
+    m[_on_plane(coords, 2, 0.0, 1.0), 2] = 1
+    top = _on_plane(coords, 2, 1.0, 1.0)
+    m[top, 2] = 1
+    vals = np.zeros((Nn, 3))
+    vals[top, 2] = strain
+    return Problem(
+        name=f"j2-roller-{nx}x{ny}x{nz}", coords=coords, conn=conn, ndpn=3, model=J2_PLASTIC,
+        theta=np.full(conn.shape[0], E), dirichlet_mask=m.ravel(), dirichlet_values=vals.ravel(), nu=nu,
+        yield_stress=yield_stress, n_load_steps=n_load_steps, krylov=CG, shape=(nx, ny, nz),
+        lengths=(1.0, 1.0, 1.0))
+
+
 def sample_elements(n_elems: int, k: int = 20, seed: int = 1) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(n_elems, size=min(k, n_elems), replace=False))
 
 
 # The five named workloads, full size.
+def poisson_inference(nx: int = 50, ny: int = 50, nz: int = 10, L=(1.0, 1.0, 0.2), alpha: float = 1.0,
+                      n_obs: int = 250, seed: int = 1, distort_seed: Optional[int] = None):
+    """Full-field inference workload: -alpha Lap u = b on the box, u = 0 on the boundary,
+    b a bimodal source of two Gaussian bumps centred at (0.25, 0.25, 0.1) and
+    (0.75, 0.75, 0.1) of the box (b = 10 exp(-1000 |x - c|^2) each), observations at
+    n_obs distinct interior nodes drawn from `seed`.  Returns (problem carrying the true
+    source as source_nodal, observed node indices)."""
+    coords, conn = box_mesh(nx, ny, nz, *L)
+    if distort_seed is not None:
+        coords = distort(coords, (nx, ny, nz), L, distort_seed)
+    bnd = np.zeros(coords.shape[0], dtype=bool)
+    for ax in range(3):
+        bnd |= _on_plane(coords, ax, 0.0, L[ax]) | _on_plane(coords, ax, L[ax], L[ax])
+    b = np.zeros(coords.shape[0])
+    for c in ((0.25 * L[0], 0.25 * L[1], 0.5 * L[2]), (0.75 * L[0], 0.75 * L[1], 0.5 * L[2])):
+        b += 10.0 * np.exp(-1000.0 * np.sum((coords - np.asarray(c)) ** 2, axis=1))
+    interior = np.flatnonzero(~bnd)
+    obs = np.sort(np.random.default_rng(seed).choice(interior, size=min(n_obs, interior.size), replace=False))
+    p = Problem(name=f"poisson-inference-{nx}x{ny}x{nz}", coords=coords, conn=conn, ndpn=1, model=POISSON,
+                theta=np.full(conn.shape[0], float(alpha)), dirichlet_mask=bnd.astype(np.uint8),
+                dirichlet_values=np.zeros(coords.shape[0]), source_nodal=b, krylov=CG, shape=(nx, ny, nz),
+                lengths=tuple(L))
+    return p, obs
+
+
 def workload(idx: int):
     if idx == 1:
         return poisson_sine(8)
