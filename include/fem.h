@@ -12,6 +12,11 @@
  *   FEM_POISSON         f = m * grad u                         (scalar, ndpn = 1)
  *   FEM_LINEAR_ELASTIC  f = lambda tr(eps) I + 2 mu eps, E = m  (Sec. 2.3, Eq. (linear_elasticity))
  *   FEM_NEO_HOOKEAN     f = P = dW/dF, G = m, kappa = bulk_ratio * m  (Sec. 2.3, Eq. (neo-hookean))
+ *   FEM_J2_PLASTIC      f = sigma^k of perfect J2 plasticity, E = m, nu, yield_stress (Sec. 2.3,
+ *                       plasticity paragraph): sigma_trial = sigma^{k-1} + lambda tr(d eps) I
+ *                       + 2 mu d eps with d eps = sym(grad u^k) - eps^{k-1}, radial return to
+ *                       the von Mises surface; (eps, sigma) at every Gauss point are the
+ *                       handle's history, committed after each converged load step
  * with a per-element modulus m(theta_e): theta_e itself (FEM_THETA_IDENTITY) or the
  * SIMP map emin + theta_e^p (e0 - emin) (FEM_THETA_SIMP, Sec. 3.3, Eq. (top_weak)).
  *
@@ -57,7 +62,7 @@ extern "C" {
 #define FEM_ENOMEM (-10)    /* device allocation failed or workspace too small */
 
 /* ---------------------------------------------------------------- enumerations */
-enum { FEM_POISSON = 0, FEM_LINEAR_ELASTIC = 1, FEM_NEO_HOOKEAN = 2 };
+enum { FEM_POISSON = 0, FEM_LINEAR_ELASTIC = 1, FEM_NEO_HOOKEAN = 2, FEM_J2_PLASTIC = 3 };
 enum { FEM_THETA_IDENTITY = 0, FEM_THETA_SIMP = 1 };
 enum { FEM_F32 = 0, FEM_F64 = 1 };
 /* Storage of tangent values.
@@ -86,10 +91,10 @@ typedef struct {
     int64_t n_nodes;
     int64_t n_elems;
     int32_t ndpn;              /* 1 for FEM_POISSON, 3 otherwise */
-    int32_t model;             /* FEM_POISSON / FEM_LINEAR_ELASTIC / FEM_NEO_HOOKEAN */
+    int32_t model;             /* FEM_POISSON / FEM_LINEAR_ELASTIC / FEM_NEO_HOOKEAN / FEM_J2_PLASTIC */
     int32_t pmap;              /* FEM_THETA_IDENTITY / FEM_THETA_SIMP */
     int32_t reserved;
-    double nu;                 /* Poisson ratio (linear elasticity) */
+    double nu;                 /* Poisson ratio (linear elasticity, J2 plasticity) */
     double bulk_ratio;         /* kappa / G (neo-Hookean) */
     double simp_p, simp_emin, simp_e0;
     const double *coords;      /* [n_nodes * 3] */
@@ -103,6 +108,7 @@ typedef struct {
                                       local face = 2*axis + side, the face where the
                                       reference coordinate xi_axis = -1 (side 0) or +1 */
     const double *traction;        /* [n_traction_faces * ndpn] constant traction per face */
+    double yield_stress;           /* sigma_yield of FEM_J2_PLASTIC (> 0); ignored otherwise */
 } fem_mesh_desc;
 
 typedef struct {
@@ -229,6 +235,26 @@ int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const d
                     size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Path-dependent state of FEM_J2_PLASTIC.  The history holds, for every element e and
+ * Gauss point q, 12 FP64 values at [(e*8 + q)*12]: the total strain of the last
+ * committed load step, then its stress, each symmetric tensor as (xx, yy, zz, yz, xz,
+ * xy).  It starts at zero and fem_newton_solve commits it after every converged load
+ * step.  fem_adjoint_vjp / fem_param_vjp are not defined for this law (FEM_EINVAL).
+ * ---------------------------------------------------------------------------- */
+
+/* Copies the history between the handle and a caller device buffer buf of
+ * n_elems * 96 doubles: into_handle = 0 reads it out (history -> buf), 1 replaces it
+ * (buf -> history; e.g. to restart a path or to reset it with zeros).  Asynchronous
+ * on stream.  FEM_EINVAL for other laws. */
+int fem_history_copy(fem_handle *h, double *buf, int32_t into_handle, void *stream);
+
+/* Volume average of the committed stress, sum_e sum_q detJ sigma_q / sum_e sum_q detJ,
+ * as (xx, yy, zz, yz, xz, xy) to the host array out[6] (the quantity the paper plots
+ * for its loading-unloading path; zeros for an empty mesh).  Blocks.  FEM_EINVAL for
+ * other laws. */
+int fem_average_stress(fem_handle *h, double *out, void *stream);
+
+/* ------------------------------------------------------------------------------
  * SIMP compliance optimisation (Sec. 4.2): the pieces around the gradient.  The
  * loop is: solve, compliance C = F_ext . u, dC/dtheta by the adjoint (lambda = u
  * for this self-adjoint objective) through fem_param_vjp, the sensitivity filter,
@@ -295,6 +321,35 @@ int fem_mma_update(int64_t n, int32_t iter, const double *x, const double *xold1
                    const double *df0, double f1, const double *df1, double *low, double *upp, double *xnew,
                    double *lambda_out, const fem_mma_opts *opts, void *workspace, size_t workspace_bytes,
                    void *stream);
+
+/* ------------------------------------------------------------------------------
+ * Full-field inference (Sec. 4.1): the source of a Poisson problem as the parameter.
+ * F(theta) = M theta with M the consistent mass of the nodal source; the adjoint of
+ * Eq. (full_field_inverse) gives dJ/dtheta = M lambda.
+ * ---------------------------------------------------------------------------- */
+
+/* y = M x: the load of the nodal field x [N] (values at the nodes, ndpn components,
+ * interpolated with the shape functions and integrated by the 2x2x2 Gauss rule, the
+ * body-source term of Eq. (weak)), on every dof including Dirichlet dofs.  x, y [N]
+ * FP64 device, distinct.  Uses the assembly workspace (fem_workspace_bytes with
+ * opts NULL).  Asynchronous. */
+int fem_mass_apply(fem_handle *h, const double *x, double *y, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Replaces the external load vector F_ext [N] (FP64 device) used by the residual and
+ * the Newton tolerance of later calls (entries on Dirichlet dofs are ignored).
+ * Blocks. */
+int fem_set_load(fem_handle *h, const double *f_ext, void *stream);
+
+/* y = a x + b y on n FP64 device entries (with b == 0, y is not read).  Current
+ * device; asynchronous. */
+int fem_axpby(int64_t n, double a, const double *x, double b, double *y, void *stream);
+
+/* Observation misfit J = sum_k (u[idx_k] - obs_k)^2 (Eq. (full_field_inverse)) to the
+ * host pointer J, and dJdu [n] (device) = 0 except 2 (u[idx_k] - obs_k) at idx_k.
+ * idx [n_obs] int64 device (distinct, < n), obs [n_obs] and u [n] FP64 device.
+ * Workspace fem_vector_workspace_bytes(n_obs).  Current device; blocks. */
+int fem_obs_misfit(int64_t n, int64_t n_obs, const int64_t *idx, const double *obs, const double *u, double *dJdu,
+                   double *J, void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -92,7 +92,9 @@ int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs,
         require(d != nullptr && out != nullptr, "desc and out must be non-NULL");
         *out = nullptr;
         require(d->n_nodes >= 0 && d->n_elems >= 0, "negative mesh size");
-        require(d->model == FEM_POISSON || d->model == FEM_LINEAR_ELASTIC || d->model == FEM_NEO_HOOKEAN, "model");
+        require(d->model == FEM_POISSON || d->model == FEM_LINEAR_ELASTIC || d->model == FEM_NEO_HOOKEAN ||
+                    d->model == FEM_J2_PLASTIC,
+                "model");
         require(d->ndpn == (d->model == FEM_POISSON ? 1 : 3), "ndpn must be 1 for FEM_POISSON and 3 otherwise");
         require(d->pmap == FEM_THETA_IDENTITY || d->pmap == FEM_THETA_SIMP, "pmap");
         require(d->n_nodes < (int64_t(1) << 31) / 3, "too many nodes for 32-bit dof indices");
@@ -102,10 +104,15 @@ int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs,
                 "traction faces");
         if (d->model == FEM_LINEAR_ELASTIC) require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
         if (d->model == FEM_NEO_HOOKEAN) require(d->bulk_ratio > 0.0, "bulk_ratio must be > 0");
+        if (d->model == FEM_J2_PLASTIC) {
+            require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
+            require(d->yield_stress > 0.0 && std::isfinite(d->yield_stress), "yield_stress must be > 0");
+        }
         h = new fem_handle();
         FEM_HIP(hipGetDevice(&h->device));
         FEM_HIP(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device));
-        h->mat = fem::Material{d->model, d->pmap, d->nu, d->bulk_ratio, d->simp_p, d->simp_emin, d->simp_e0};
+        h->mat = fem::Material{d->model,   d->pmap,      d->nu,      d->bulk_ratio,
+                               d->simp_p, d->simp_emin, d->simp_e0, d->yield_stress};
         const int64_t N = d->n_nodes * d->ndpn;
         // every node must belong to an element (otherwise its row has no diagonal)
         {
@@ -287,6 +294,7 @@ int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const d
         validate_opts(opts);
         if (stats) std::memset(stats, 0, sizeof(*stats));
         if (h->g.N == 0) return;
+        require(h->mat.model != FEM_J2_PLASTIC, "the adjoint is not defined for FEM_J2_PLASTIC");
         require(u && theta && dJdu && vjp_theta, "u, theta, dJdu and vjp_theta must be non-NULL");
         check_workspace(h, opts, workspace, workspace_bytes);
         bind_device(h);
@@ -295,10 +303,36 @@ int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const d
     });
 }
 
+int fem_history_copy(fem_handle *h, double *buf, int32_t into_handle, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        require(h->mat.model == FEM_J2_PLASTIC, "the handle's law has no history (FEM_J2_PLASTIC only)");
+        require(into_handle == 0 || into_handle == 1, "into_handle must be 0 or 1");
+        if (h->g.Ne == 0) return;
+        require(buf != nullptr, "buf is NULL");
+        bind_device(h);
+        const size_t bytes = size_t(h->g.Ne) * 96 * sizeof(double);
+        if (into_handle)
+            FEM_HIP(hipMemcpyAsync(h->hist, buf, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+        else
+            FEM_HIP(hipMemcpyAsync(buf, h->hist, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+    });
+}
+
+int fem_average_stress(fem_handle *h, double *out, void *stream) {
+    return guarded([&] {
+        require(h != nullptr && out != nullptr, "handle and out must be non-NULL");
+        require(h->mat.model == FEM_J2_PLASTIC, "the handle's law has no history (FEM_J2_PLASTIC only)");
+        bind_device(h);
+        fem::j2_average_stress(h, out, as_stream(stream));
+    });
+}
+
 int fem_param_vjp(fem_handle *h, const double *u, const double *theta, const double *lambda, double *vjp_theta,
                   void *stream) {
     return guarded([&] {
         require(h != nullptr, "handle is NULL");
+        require(h->mat.model != FEM_J2_PLASTIC, "the parameter VJP is not defined for FEM_J2_PLASTIC");
         if (h->g.Ne == 0) return;
         require(u && theta && lambda && vjp_theta, "u, theta, lambda and vjp_theta must be non-NULL");
         bind_device(h);
@@ -391,6 +425,53 @@ int fem_mma_update(int64_t n, int32_t iter, const double *x, const double *xold1
         const double lam = fem::mma_update(n, iter, x, xold1, xold2, df0, f1, df1, low, upp, xnew, *opts, workspace,
                                            as_stream(stream));
         if (lambda_out) *lambda_out = lam;
+    });
+}
+
+int fem_mass_apply(fem_handle *h, const double *x, double *y, void *workspace, size_t workspace_bytes, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        if (h->g.N == 0) return;
+        require(x && y && x != y, "x and y must be distinct non-NULL buffers");
+        check_workspace(h, nullptr, workspace, workspace_bytes);
+        bind_device(h);
+        void *ke;
+        double *rscr;
+        fem::carve_assemble(h, workspace, workspace_bytes, &ke, &rscr, FEM_F64);
+        fem::reset_status(h, as_stream(stream));
+        fem::launch_mass(h, x, rscr, y, as_stream(stream));
+        fem::check_status(h, as_stream(stream));
+    });
+}
+
+int fem_set_load(fem_handle *h, const double *f_ext, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        if (h->g.N == 0) return;
+        require(f_ext != nullptr, "f_ext must be non-NULL");
+        bind_device(h);
+        fem::set_load(h, f_ext, as_stream(stream));
+    });
+}
+
+int fem_axpby(int64_t n, double a, const double *x, double b, double *y, void *stream) {
+    return guarded([&] {
+        require(n >= 0, "n must be >= 0");
+        if (n == 0) return;
+        require(x && y, "x and y must be non-NULL");
+        fem::axpby(n, a, x, b, y, as_stream(stream));
+    });
+}
+
+int fem_obs_misfit(int64_t n, int64_t n_obs, const int64_t *idx, const double *obs, const double *u, double *dJdu,
+                   double *J, void *workspace, size_t workspace_bytes, void *stream) {
+    return guarded([&] {
+        require(J != nullptr, "J is NULL");
+        require(n >= 0 && n_obs >= 0, "sizes must be >= 0");
+        *J = 0.0;
+        require(u && dJdu && (n_obs == 0 || (idx && obs)), "vector arguments must be non-NULL");
+        require(workspace && workspace_bytes >= fem::vector_workspace_bytes(n_obs), "workspace too small");
+        *J = fem::obs_misfit(n, n_obs, idx, obs, u, dJdu, workspace, as_stream(stream));
     });
 }
 

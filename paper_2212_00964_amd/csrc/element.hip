@@ -16,6 +16,7 @@
 // Paper: element residual R_e and K_e = dr_e/dU_e (Sec. 2.2), constitutive laws
 // (Sec. 2.3, Eq. (linear_elasticity), Eq. (neo-hookean)), assembly (Alg. 1).
 #include <algorithm>
+#include <vector>
 
 #include "internal.h"
 #include "lanes.h"
@@ -141,10 +142,64 @@ __device__ __forceinline__ void matvec3(const T A[3][3], const T x[3], T y[3]) {
     for (int i = 0; i < 3; ++i) y[i] = A[i][0] * x[0] + A[i][1] * x[1] + A[i][2] * x[2];
 }
 
+// Perfect J2 plasticity at one Gauss point (Sec. 2.3, plasticity paragraph).  hq holds
+// the committed state of the point: total strain then stress, each as (xx, yy, zz, yz,
+// xz, xy).  Trial stress from the strain increment sym(G) - eps, deviator s and
+// s_vm = sqrt(3/2 s:s); above the yield stress the deviator is scaled back onto the
+// surface (radial return).  The consistent tangent of that map, d sigma / d grad u
+// (hand-derived; the paper leaves it to automatic differentiation), is
+//   A = lw I(x)I + mup (delta_ik delta_jl + delta_il delta_jk) - beta s(x)s
+// with kappa = lambda + 2 mu / 3; elastic: mup = mu, beta = 0; plastic:
+// mup = mu sigma_y / s_vm, beta = 3 mup / s_vm^2; and lw = kappa - 2 mup / 3.
+template <typename T>
+struct J2State {
+    T sig[6], dev[6];  // returned stress and trial deviator, (xx, yy, zz, yz, xz, xy)
+    T lw, mup, beta;
+};
+
+template <typename T>
+__device__ __forceinline__ void j2_state(const Material &m, T E, const T G[3][3], const double *hq, J2State<T> &s) {
+    const T nu = T(m.nu);
+    const T lam = E * nu / ((T(1) + nu) * (T(1) - T(2) * nu)), mu = E / (T(2) * (T(1) + nu));
+    T de[6] = {G[0][0], G[1][1], G[2][2], T(0.5) * (G[1][2] + G[2][1]), T(0.5) * (G[0][2] + G[2][0]),
+               T(0.5) * (G[0][1] + G[1][0])};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) de[c] -= T(hq[c]);
+    const T tr = de[0] + de[1] + de[2];
+    T st[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) st[c] = T(hq[6 + c]) + T(2) * mu * de[c] + (c < 3 ? lam * tr : T(0));
+    const T p = (st[0] + st[1] + st[2]) * T(1.0 / 3.0);
+    T ss = T(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        s.dev[c] = st[c] - (c < 3 ? p : T(0));
+        ss += (c < 3 ? T(1) : T(2)) * s.dev[c] * s.dev[c];
+    }
+    const T svm = sqrt(T(1.5) * ss), f = svm - T(m.yield_stress);
+    const bool plastic = f > T(0);
+    const T kappa = lam + T(2.0 / 3.0) * mu;
+    s.mup = plastic ? mu * T(m.yield_stress) / svm : mu;
+    s.beta = plastic ? T(3) * s.mup / (svm * svm) : T(0);
+    s.lw = kappa - T(2.0 / 3.0) * s.mup;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s.sig[c] = plastic ? st[c] - s.dev[c] / svm * f : st[c];
+}
+
+// y = S x for a symmetric tensor stored as (xx, yy, zz, yz, xz, xy).
+template <typename T>
+__device__ __forceinline__ void symvec(const T S[6], const T x[3], T y[3]) {
+    y[0] = S[0] * x[0] + S[5] * x[1] + S[4] * x[2];
+    y[1] = S[5] * x[0] + S[1] * x[1] + S[3] * x[2];
+    y[2] = S[4] * x[0] + S[3] * x[1] + S[2] * x[2];
+}
+
 // Flux applied to this lane's shape gradient: out = f(G) g (the integrand of R_e
 // at one Gauss point, before the quadrature weight).  Returns false if det F <= 0.
+// hq: the Gauss point's committed J2 state (unused by the other laws).
 template <int MODEL, typename T>
-__device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][3], const T g[3], T out[3]) {
+__device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][3], const T g[3], T out[3],
+                                         const double *hq) {
     if constexpr (MODEL == FEM_POISSON) {
         out[0] = mod * (G[0][0] * g[0] + G[0][1] * g[1] + G[0][2] * g[2]);
         out[1] = out[2] = T(0);
@@ -157,6 +212,11 @@ __device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][
         for (int i = 0; i < 3; ++i)
             out[i] = lam * tr * g[i] + mu * ((G[i][0] + G[0][i]) * g[0] + (G[i][1] + G[1][i]) * g[1] +
                                              (G[i][2] + G[2][i]) * g[2]);
+        return true;
+    } else if constexpr (MODEL == FEM_J2_PLASTIC) {
+        J2State<T> s;
+        j2_state(m, mod, G, hq, s);
+        symvec(s.sig, g, out);
         return true;
     } else {
         NHState<T> s;
@@ -173,9 +233,25 @@ __device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][
 // Directional derivative of the flux: out = (A : dG) g with A the tangent at G.
 template <int MODEL, typename T>
 __device__ __forceinline__ bool dflux_dot(const Material &m, T mod, const T G[3][3], const T dG[3][3], const T g[3],
-                                          T out[3]) {
-    if constexpr (MODEL != FEM_NEO_HOOKEAN) {
-        return flux_dot<MODEL, T>(m, mod, dG, g, out);  // linear laws
+                                          T out[3], const double *hq) {
+    if constexpr (MODEL == FEM_POISSON || MODEL == FEM_LINEAR_ELASTIC) {
+        return flux_dot<MODEL, T>(m, mod, dG, g, out, hq);  // linear laws
+    } else if constexpr (MODEL == FEM_J2_PLASTIC) {
+        J2State<T> s;
+        j2_state(m, mod, G, hq, s);
+        const T tr = dG[0][0] + dG[1][1] + dG[2][2];
+        const T sd = s.dev[0] * dG[0][0] + s.dev[1] * dG[1][1] + s.dev[2] * dG[2][2] +
+                     s.dev[3] * (dG[1][2] + dG[2][1]) + s.dev[4] * (dG[0][2] + dG[2][0]) +
+                     s.dev[5] * (dG[0][1] + dG[1][0]);
+        T sg[3];
+        symvec(s.dev, g, sg);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            out[i] = s.lw * tr * g[i] +
+                     s.mup * ((dG[i][0] + dG[0][i]) * g[0] + (dG[i][1] + dG[1][i]) * g[1] +
+                              (dG[i][2] + dG[2][i]) * g[2]) -
+                     s.beta * sd * sg[i];
+        return true;
     } else {
         NHState<T> s;
         bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
@@ -239,7 +315,7 @@ __device__ __forceinline__ void load_node(const double *coords, const int32_t *c
 }
 
 // ------------------------------------------------------------------ residual-type kernels
-enum { VEC_RESIDUAL = 0, VEC_JVP = 1, VEC_VJP = 2, VEC_LIFT = 3 };
+enum { VEC_RESIDUAL = 0, VEC_JVP = 1, VEC_VJP = 2, VEC_LIFT = 3, VEC_MASS = 4 };
 
 // (slot s = kpos[e*8 + a]: node-major incidence order, so each node's terms are contiguous)
 // VEC_RESIDUAL: scratch[s][i] = sum_q detJ f(grad u) g_a            (modulus m(theta_e))
@@ -253,7 +329,8 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
                                                           const uint8_t *__restrict__ mask, Material mat,
                                                           const double *__restrict__ theta,
                                                           const double *__restrict__ u,
-                                                          const double *__restrict__ v, double *__restrict__ out,
+                                                          const double *__restrict__ v,
+                                                          const double *__restrict__ hist, double *__restrict__ out,
                                                           int *status) {
     ElemIds id = elem_ids(Ne);
     double X[3], U[ND], W[ND];
@@ -271,12 +348,13 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
         mesh_ok &= dJ > 0.0;
         double G[3][3], o[3];
         field_grad<ND>(U, g, G);
+        const double *hq = MODEL == FEM_J2_PLASTIC ? hist + (id.e * 8 + q) * 12 : nullptr;
         if (MODE == VEC_JVP || MODE == VEC_LIFT) {
             double dG[3][3];
             field_grad<ND>(W, g, dG);
-            mat_ok &= dflux_dot<MODEL, double>(mat, mod, G, dG, g, o);
+            mat_ok &= dflux_dot<MODEL, double>(mat, mod, G, dG, g, o, hq);
         } else {
-            mat_ok &= flux_dot<MODEL, double>(mat, mod, G, g, o);
+            mat_ok &= flux_dot<MODEL, double>(mat, mod, G, g, o, hq);
         }
 #pragma unroll
         for (int i = 0; i < ND; ++i) acc[i] += dJ * o[i];
@@ -292,6 +370,116 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
     } else if (id.valid) {
 #pragma unroll
         for (int i = 0; i < ND; ++i) out[int64_t(kpos[id.e * 8 + id.a]) * ND + i] = acc[i];
+    }
+}
+
+// Consistent mass product: scratch[s][i] = sum_q detJ N_a(xi_q) sum_b N_b(xi_q) x_b,i
+// (the load of a nodal field x interpolated with the shape functions; Sec. 2.1,
+// the body-force term of Eq. (weak)).
+template <int ND>
+__global__ __launch_bounds__(kThreads) void k_element_mass(int64_t Ne, const double *__restrict__ coords,
+                                                           const int32_t *__restrict__ conn,
+                                                           const int32_t *__restrict__ kpos,
+                                                           const double *__restrict__ x, double *__restrict__ out,
+                                                           int *status) {
+    ElemIds id = elem_ids(Ne);
+    double X[3], Xv[ND];
+    load_node<ND, double>(coords, conn, x, nullptr, id, X, Xv, false);
+    const double gq = 0.57735026918962576451;
+    double acc[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) acc[i] = 0.0;
+    bool mesh_ok = true;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        double g[3];
+        const double dJ = gp_geometry(id.a, q, X, g);
+        mesh_ok &= dJ > 0.0;
+        double Na = 1.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double xi = (q >> j) & 1 ? gq : -gq;
+            Na *= 0.5 * (1.0 + double(ref_sign(id.a, j)) * xi);
+        }
+#pragma unroll
+        for (int i = 0; i < ND; ++i) acc[i] += dJ * Na * sum8(Na * Xv[i]);
+    }
+    if (id.valid && id.a == 0 && !mesh_ok) atomicOr(status, ST_MESH);
+    if (id.valid)
+#pragma unroll
+        for (int i = 0; i < ND; ++i) out[int64_t(kpos[id.e * 8 + id.a]) * ND + i] = acc[i];
+}
+
+// J2 history commit after a converged load step: lane a updates Gauss point a of its
+// element, eps <- sym(grad u) and sigma <- the returned stress of j2_state.  Each
+// point reads and then writes only its own record, so the update is in place.
+__global__ __launch_bounds__(kThreads) void k_j2_commit(int64_t Ne, const double *__restrict__ coords,
+                                                       const int32_t *__restrict__ conn, Material mat,
+                                                       const double *__restrict__ theta,
+                                                       const double *__restrict__ u, double *__restrict__ hist) {
+    ElemIds id = elem_ids(Ne);
+    double X[3], U[3];
+    load_node<3, double>(coords, conn, u, nullptr, id, X, U, true);
+    double Gm[3][3] = {};
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        double g[3], G[3][3];
+        gp_geometry(id.a, q, X, g);
+        field_grad<3>(U, g, G);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Gm[i][j] = (q == id.a) ? G[i][j] : Gm[i][j];
+    }
+    if (!id.valid) return;
+    double *hq = hist + (id.e * 8 + id.a) * 12;
+    J2State<double> st;
+    j2_state(mat, modulus(mat, theta[id.e]), Gm, hq, st);
+    const double eps[6] = {Gm[0][0], Gm[1][1], Gm[2][2], 0.5 * (Gm[1][2] + Gm[2][1]), 0.5 * (Gm[0][2] + Gm[2][0]),
+                           0.5 * (Gm[0][1] + Gm[1][0])};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        hq[c] = eps[c];
+        hq[6 + c] = st.sig[c];
+    }
+}
+
+// Per-block partial sums of sum_q detJ sigma_q (6 components) and sum_q detJ over the
+// committed J2 history: lane a takes Gauss point a; partials[block * 7 + c].
+__global__ __launch_bounds__(kThreads) void k_j2_average(int64_t Ne, const double *__restrict__ coords,
+                                                        const int32_t *__restrict__ conn,
+                                                        const double *__restrict__ hist, double *partials) {
+    __shared__ double red[kThreads / 64][7];
+    ElemIds id = elem_ids(Ne);
+    double X[3], U[1];
+    load_node<1, double>(coords, conn, nullptr, nullptr, id, X, U, false);
+    double w = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        double g[3];
+        const double dJ = gp_geometry(id.a, q, X, g);
+        w = (q == id.a) ? dJ : w;
+    }
+    if (!id.valid) w = 0.0;
+    const double *hs = hist + (id.e * 8 + id.a) * 12 + 6;
+    double v[7];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = w * hs[c];
+    v[6] = w;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
+    }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) red[threadIdx.x >> 6][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kThreads / 64; ++k) t += red[k][threadIdx.x];
+        partials[int64_t(blockIdx.x) * 7 + threadIdx.x] = t;
     }
 }
 
@@ -330,14 +518,18 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
                                                               const int32_t *__restrict__ conn,
                                                               const int32_t *__restrict__ kpos, Material mat,
                                                               const double *__restrict__ theta,
-                                                              const double *__restrict__ u, T *__restrict__ ke,
+                                                              const double *__restrict__ u,
+                                                              const double *__restrict__ hist, T *__restrict__ ke,
                                                               int *status) {
-    constexpr int NV = (MODEL == FEM_NEO_HOOKEAN) ? 9 : 3;  // per-node data shared through LDS
-    constexpr int ES = 8 * NV + 1;                          // padded element stride (bank spread)
+    // per-node data shared through LDS: g (all laws), F g and F^{-T} g (neo-Hookean),
+    // s g with the trial deviator s (J2)
+    constexpr int NV = (MODEL == FEM_NEO_HOOKEAN) ? 9 : (MODEL == FEM_J2_PLASTIC ? 6 : 3);
+    constexpr int ES = 8 * NV + 1;  // padded element stride (bank spread)
+    constexpr bool kNonlinear = MODEL == FEM_NEO_HOOKEAN || MODEL == FEM_J2_PLASTIC;
     __shared__ T lds[kElemsPerBlock * ES];
     ElemIds id = elem_ids(Ne);
     T X[3], U[ND];
-    load_node<ND, T>(coords, conn, MODEL == FEM_NEO_HOOKEAN ? u : nullptr, nullptr, id, X, U, true);
+    load_node<ND, T>(coords, conn, kNonlinear ? u : nullptr, nullptr, id, X, U, true);
     T mod = T(modulus(mat, theta[id.e]));
     T K[8][ND][ND];
 #pragma unroll
@@ -380,6 +572,35 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         T v = aw * h[i] * hb[k] + bw * hb[i] * h[k] - c23 * (f[i] * hb[k] + h[i] * fb[k]);
+                        if (i == k) v += sdot;
+                        K[b][i][k] += v;
+                    }
+            }
+            __syncthreads();
+        } else if constexpr (MODEL == FEM_J2_PLASTIC) {
+            T G[3][3];
+            field_grad<ND>(U, g, G);
+            J2State<T> s;
+            j2_state(mat, mod, G, hist + (id.e * 8 + q) * 12, s);
+            T sg[3];
+            symvec(s.dev, g, sg);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                my[i] = g[i];
+                my[3 + i] = sg[i];
+            }
+            __syncthreads();
+            T lw = dJ * s.lw, mw = dJ * s.mup, bw = dJ * s.beta;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const T *o = el + b * NV;
+                T gb[3] = {o[0], o[1], o[2]}, sb[3] = {o[3], o[4], o[5]};
+                T sdot = mw * (g[0] * gb[0] + g[1] * gb[1] + g[2] * gb[2]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        T v = lw * g[i] * gb[k] + mw * g[k] * gb[i] - bw * sg[i] * sb[k];
                         if (i == k) v += sdot;
                         K[b][i][k] += v;
                     }
@@ -669,6 +890,7 @@ inline unsigned gather_grid(const fem_handle *h) {
     switch ((h)->mat.model) {                                                                        \
     case FEM_POISSON: { constexpr int MODEL = FEM_POISSON; constexpr int ND = 1; CALL; break; }      \
     case FEM_LINEAR_ELASTIC: { constexpr int MODEL = FEM_LINEAR_ELASTIC; constexpr int ND = 3; CALL; break; } \
+    case FEM_J2_PLASTIC: { constexpr int MODEL = FEM_J2_PLASTIC; constexpr int ND = 3; CALL; break; }        \
     default: { constexpr int MODEL = FEM_NEO_HOOKEAN; constexpr int ND = 3; CALL; break; }          \
     }
 
@@ -682,7 +904,8 @@ void launch_residual(const fem_handle *h, const double *u, const double *theta, 
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_RESIDUAL>), dim3(gridE), dim3(kThreads), 0, s, g.Ne,
-                           h->m.coords, h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, nullptr, scratch, h->status);
+                           h->m.coords, h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, nullptr, h->hist, scratch,
+                           h->status);
         hipLaunchKernelGGL((k_gather_vec<ND, VEC_RESIDUAL>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N,
                            g.ne_ptr, scratch, h->m.mask, h->m.fext, lf, nullptr, r, h->status);
     });
@@ -699,7 +922,7 @@ void launch_apply_tangent(const fem_handle *h, const double *u, const double *th
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_JVP>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
-                           h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, v, scratch, h->status);
+                           h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, v, h->hist, scratch, h->status);
         hipLaunchKernelGGL((k_gather_vec<ND, VEC_JVP>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
                            scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
     });
@@ -713,21 +936,72 @@ void launch_lift(const fem_handle *h, const double *u, const double *theta, cons
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_LIFT>), dim3(gridE), dim3(kThreads), 0, s, g.Ne,
-                           h->m.coords, h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, v, scratch, h->status);
+                           h->m.coords, h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, v, h->hist, scratch, h->status);
         hipLaunchKernelGGL((k_gather_vec<ND, VEC_LIFT>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
                            scratch, h->m.mask, nullptr, 0.0, v, y, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
 
+void launch_mass(const fem_handle *h, const double *x, double *scratch, double *y, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0) {
+        FEM_HIP(hipMemsetAsync(y, 0, g.N * sizeof(double), s));
+        return;
+    }
+    unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
+    if (g.nd == 1) {
+        hipLaunchKernelGGL((k_element_mass<1>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords, h->m.conn,
+                           g.kpos, x, scratch, h->status);
+        hipLaunchKernelGGL((k_gather_vec<1, VEC_MASS>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
+                           scratch, nullptr, nullptr, 0.0, nullptr, y, h->status);
+    } else {
+        hipLaunchKernelGGL((k_element_mass<3>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords, h->m.conn,
+                           g.kpos, x, scratch, h->status);
+        hipLaunchKernelGGL((k_gather_vec<3, VEC_MASS>), dim3(grid_for(g.N, 256)), dim3(256), 0, s, g.N, g.ne_ptr,
+                           scratch, nullptr, nullptr, 0.0, nullptr, y, h->status);
+    }
+    FEM_HIP(hipGetLastError());
+}
+
+void launch_j2_commit(const fem_handle *h, const double *u, const double *theta, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Ne == 0 || h->mat.model != FEM_J2_PLASTIC) return;
+    hipLaunchKernelGGL(k_j2_commit, dim3(grid_for(g.Ne, kElemsPerBlock)), dim3(kThreads), 0, s, g.Ne, h->m.coords,
+                       h->m.conn, h->mat, theta, u, h->hist);
+    FEM_HIP(hipGetLastError());
+}
+
+void j2_average_stress(fem_handle *h, double out[6], hipStream_t s) {
+    const Graph &g = h->g;
+    for (int c = 0; c < 6; ++c) out[c] = 0.0;
+    if (g.Ne == 0) return;
+    const unsigned grid = grid_for(g.Ne, kElemsPerBlock);
+    if (!h->hist_partials) {
+        FEM_HIP(hipMalloc(reinterpret_cast<void **>(&h->hist_partials), size_t(grid) * 7 * sizeof(double)));
+        h->allocations.push_back(h->hist_partials);
+    }
+    hipLaunchKernelGGL(k_j2_average, dim3(grid), dim3(kThreads), 0, s, g.Ne, h->m.coords, h->m.conn, h->hist,
+                       h->hist_partials);
+    FEM_HIP(hipGetLastError());
+    std::vector<double> hp(size_t(grid) * 7);
+    FEM_HIP(hipMemcpyAsync(hp.data(), h->hist_partials, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    double t[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (unsigned b = 0; b < grid; ++b)
+        for (int c = 0; c < 7; ++c) t[c] += hp[size_t(b) * 7 + c];
+    for (int c = 0; c < 6; ++c) out[c] = t[c] / t[6];
+}
+
 void launch_vjp(const fem_handle *h, const double *u, const double *theta, const double *lam, double *gout,
                 hipStream_t s) {
     const Graph &g = h->g;
     if (g.Ne == 0) return;
+    if (h->mat.model == FEM_J2_PLASTIC) throw Error(FEM_EINVAL, "the parameter VJP is not defined for FEM_J2_PLASTIC");
     unsigned gridE = grid_for(g.Ne, kElemsPerBlock);
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_vec<MODEL, ND, VEC_VJP>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
-                           h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, lam, gout, h->status);
+                           h->m.conn, g.kpos, h->m.mask, h->mat, theta, u, lam, nullptr, gout, h->status);
     });
     FEM_HIP(hipGetLastError());
 }
@@ -742,7 +1016,7 @@ void launch_tangent(const fem_handle *h, const double *u, const double *theta, T
     const bool node_gather = g.tgt != nullptr && g.max_deg <= kGatherMaxDeg;
     FEM_DISPATCH_MODEL(h, {
         hipLaunchKernelGGL((k_element_tangent<MODEL, ND, T>), dim3(gridE), dim3(kThreads), 0, s, g.Ne, h->m.coords,
-                           h->m.conn, g.kpos, h->mat, theta, u, ke, h->status);
+                           h->m.conn, g.kpos, h->mat, theta, u, h->hist, ke, h->status);
         if (node_gather) {
             if (layout == LAYOUT_SYM)
                 hipLaunchKernelGGL((k_gather_node<ND, LAYOUT_SYM, T>), dim3(gather_grid(h)), dim3(256), 0, s,

@@ -37,6 +37,7 @@ enum Layout { LAYOUT_CSR = 0, LAYOUT_SYM = 1 };
 struct Material {
     int model, pmap;
     double nu, bulk_ratio, simp_p, simp_emin, simp_e0;
+    double yield_stress;  // J2 plasticity
 };
 
 // Device-side Krylov scalars (FP64), one instance per solve in the workspace.
@@ -119,6 +120,8 @@ struct fem_handle {
     std::vector<void *> allocations;          // device allocations owned by the handle
     fem::Filter filter;                       // fem_filter_setup (owns its allocations)
     double *red_partials = nullptr;           // reduction partials of fem_element_volumes (lazy)
+    double *hist = nullptr;                   // J2 history [Ne*8*12] (eps, sigma per Gauss point)
+    double *hist_partials = nullptr;          // per-block partials of fem_average_stress (lazy)
 };
 
 namespace fem {
@@ -144,8 +147,13 @@ void launch_tangent(const fem_handle *h, const double *u, const double *theta, T
 // y = (K(u) v) on free dofs with v used on every dof (Dirichlet lifting), 0 on Dirichlet dofs.
 void launch_lift(const fem_handle *h, const double *u, const double *theta, const double *v, double *scratch,
                  double *y, hipStream_t s);
+// y = M x (consistent mass of a nodal field, all dofs), scratch [Ne*8*nd] FP64.
+void launch_mass(const fem_handle *h, const double *x, double *scratch, double *y, hipStream_t s);
 void launch_vjp(const fem_handle *h, const double *u, const double *theta, const double *lam, double *g,
                 hipStream_t s);
+// J2: commit the history at u (after a converged load step); volume-averaged stress.
+void launch_j2_commit(const fem_handle *h, const double *u, const double *theta, hipStream_t s);
+void j2_average_stress(fem_handle *h, double out[6], hipStream_t s);
 template <typename T>
 void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s, int layout = LAYOUT_CSR);
 
@@ -190,6 +198,10 @@ void element_volumes(fem_handle *h, double *vol, bool normalized, hipStream_t s)
 void filter_setup(fem_handle *h, double rmin);
 void filter_apply(const fem_handle *h, int mode, const double *theta, const double *x, double *out, hipStream_t s);
 double dot(const double *a, const double *b, int64_t n, void *ws, hipStream_t s);
+void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+double obs_misfit(int64_t n, int64_t n_obs, const int64_t *idx, const double *obs, const double *u, double *dJdu,
+                  void *ws, hipStream_t s);
+void set_load(fem_handle *h, const double *f, hipStream_t s);
 double mma_update(int64_t n, int iter, const double *x, const double *xold1, const double *xold2, const double *df0,
                   double f1, const double *df1, double *low, double *upp, double *xnew, const fem_mma_opts &o,
                   void *ws, hipStream_t s);

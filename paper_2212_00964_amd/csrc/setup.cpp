@@ -264,6 +264,11 @@ void build_load_vector(fem_handle *h, const fem_mesh_desc *d) {
         if (!(d->dirichlet_mask && d->dirichlet_mask[i])) nrm += F[i] * F[i];
     h->m.fext_norm = std::sqrt(nrm);
     h->m.fext = upload(h, F);
+    if (d->model == FEM_J2_PLASTIC) {  // history of the path, zero (unstressed) at the start
+        const size_t bytes = size_t(d->n_elems) * 96 * sizeof(double);
+        h->hist = static_cast<double *>(dev_alloc(h, bytes));
+        FEM_HIP(hipMemset(h->hist, 0, bytes == 0 ? 256 : bytes));
+    }
 }
 
 }  // namespace fem

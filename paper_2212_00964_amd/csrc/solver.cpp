@@ -303,6 +303,7 @@ static void newton_impl(fem_handle *h, double *u, const double *theta, const dou
             ++it;
         }
         if (st) st->final_residual = rn;
+        launch_j2_commit(h, u, theta, s);  // path-dependent laws: the converged step becomes the history
     }
     if (st) st->ms_total += ms_since(t_all);
 }

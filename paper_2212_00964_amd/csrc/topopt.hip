@@ -104,6 +104,40 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, double c, double 
     if (i < n) a[i] *= c;
 }
 
+__global__ __launch_bounds__(kThreads) void k_axpby(int64_t n, double a, const double *__restrict__ x, double b,
+                                                   double *__restrict__ y) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(int64_t n, double v, double *__restrict__ y) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+// Misfit at observed dofs: r_k = u[idx_k] - obs_k; dJdu[idx_k] = 2 r_k (dJdu zeroed
+// before); partials of sum r_k^2.  The observed indices are distinct.
+__global__ __launch_bounds__(kThreads) void k_obs_misfit(int64_t n_obs, const int64_t *__restrict__ idx,
+                                                        const double *__restrict__ obs, const double *__restrict__ u,
+                                                        double *__restrict__ dJdu, double *partials) {
+    double acc = 0.0;
+    for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n_obs; k += int64_t(gridDim.x) * kThreads) {
+        const double r = u[idx[k]] - obs[k];
+        dJdu[idx[k]] = 2.0 * r;
+        acc += r * r;
+    }
+    block_partial(acc, partials);
+}
+
+// sum of squares over the dofs that are not Dirichlet dofs (mask may be null)
+__global__ __launch_bounds__(kThreads) void k_sumsq_free(int64_t n, const double *__restrict__ a,
+                                                        const uint8_t *__restrict__ mask, double *partials) {
+    double d = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += int64_t(gridDim.x) * kThreads)
+        if (!(mask && mask[i])) d += a[i] * a[i];
+    block_partial(d, partials);
+}
+
 // ------------------------------------------------------------------ MMA
 struct MmaArrays {
     double *alpha, *beta, *p0, *q0, *p1, *q1;
@@ -320,6 +354,34 @@ double dot(const double *a, const double *b, int64_t n, void *ws, hipStream_t s)
     hipLaunchKernelGGL(k_dot, dim3(kRedGrid), dim3(kThreads), 0, s, n, a, b, partials);
     FEM_HIP(hipGetLastError());
     return host_sum(partials, pinned_partials(), s);
+}
+
+void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y);
+    FEM_HIP(hipGetLastError());
+}
+
+double obs_misfit(int64_t n, int64_t n_obs, const int64_t *idx, const double *obs, const double *u, double *dJdu,
+                  void *ws, hipStream_t s) {
+    double *partials = static_cast<double *>(ws);
+    if (n) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kThreads), 0, s, n, 0.0, dJdu);
+    hipLaunchKernelGGL(k_obs_misfit, dim3(kRedGrid), dim3(kThreads), 0, s, n_obs, idx, obs, u, dJdu, partials);
+    FEM_HIP(hipGetLastError());
+    return host_sum(partials, pinned_partials(), s);
+}
+
+void set_load(fem_handle *h, const double *f, hipStream_t s) {
+    const int64_t N = h->g.N;
+    if (N == 0) return;
+    FEM_HIP(hipMemcpyAsync(h->m.fext, f, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (!h->red_partials) {
+        FEM_HIP(hipMalloc(reinterpret_cast<void **>(&h->red_partials), kRedGrid * sizeof(double)));
+        h->allocations.push_back(h->red_partials);
+    }
+    hipLaunchKernelGGL(k_sumsq_free, dim3(kRedGrid), dim3(kThreads), 0, s, N, h->m.fext, h->m.mask, h->red_partials);
+    FEM_HIP(hipGetLastError());
+    h->m.fext_norm = std::sqrt(host_sum(h->red_partials, pinned_partials(), s));
 }
 
 double mma_update(int64_t n, int iter, const double *x, const double *xold1, const double *xold2, const double *df0,

@@ -48,7 +48,7 @@ class MeshDesc(ctypes.Structure):
                 ("simp_emin", ctypes.c_double), ("simp_e0", ctypes.c_double), ("coords", ctypes.c_void_p),
                 ("conn", ctypes.c_void_p), ("dirichlet_mask", ctypes.c_void_p), ("f_nodal", ctypes.c_void_p),
                 ("source_nodal", ctypes.c_void_p), ("n_traction_faces", ctypes.c_int64),
-                ("traction_faces", ctypes.c_void_p), ("traction", ctypes.c_void_p)]
+                ("traction_faces", ctypes.c_void_p), ("traction", ctypes.c_void_p), ("yield_stress", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -87,9 +87,10 @@ class MmaOpts(ctypes.Structure):
 # Names, in the order the header declares them (checked by the CPU test-suite).
 EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
            "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv",
-           "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_param_vjp", "fem_element_volumes",
+           "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_history_copy", "fem_average_stress",
+           "fem_param_vjp", "fem_element_volumes",
            "fem_filter_setup", "fem_filter_apply", "fem_vector_workspace_bytes", "fem_dot", "fem_mma_default_opts",
-           "fem_mma_update"]
+           "fem_mma_update", "fem_mass_apply", "fem_set_load", "fem_axpby", "fem_obs_misfit"]
 
 _lib = None
 
@@ -122,6 +123,8 @@ def lib():
         "fem_apply_tangent": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "fem_newton_solve": (ctypes.c_int, [vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
         "fem_adjoint_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
+        "fem_history_copy": (ctypes.c_int, [vp, vp, i32, vp]),
+        "fem_average_stress": (ctypes.c_int, [vp, P(dbl), vp]),
         "fem_param_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "fem_element_volumes": (ctypes.c_int, [vp, vp, i32, vp]),
         "fem_filter_setup": (ctypes.c_int, [vp, dbl]),
@@ -131,6 +134,10 @@ def lib():
         "fem_mma_default_opts": (ctypes.c_int, [P(MmaOpts)]),
         "fem_mma_update": (ctypes.c_int, [i64, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp, P(dbl), P(MmaOpts), vp, sz,
                                           vp]),
+        "fem_mass_apply": (ctypes.c_int, [vp, vp, vp, vp, sz, vp]),
+        "fem_set_load": (ctypes.c_int, [vp, vp, vp]),
+        "fem_axpby": (ctypes.c_int, [i64, dbl, vp, dbl, vp, vp]),
+        "fem_obs_misfit": (ctypes.c_int, [i64, i64, vp, vp, vp, vp, P(dbl), vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -205,6 +212,24 @@ def mma_update(it: int, x, xold1, xold2, df0, f1: float, df1, low, upp, opts: Op
     return xnew, lam.value
 
 
+def axpby(a: float, x: torch.Tensor, b: float, y: torch.Tensor) -> torch.Tensor:
+    """y = a x + b y in place on float64 device vectors (fem_axpby); returns y."""
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or x.numel() != y.numel():
+        raise ValueError("axpby needs two float64 vectors of equal length")
+    _check(lib().fem_axpby(x.numel(), float(a), _ptr(x), float(b), _ptr(y), _stream()))
+    return y
+
+
+def obs_misfit(u: torch.Tensor, idx: torch.Tensor, obs: torch.Tensor, dJdu: torch.Tensor,
+               workspace: Optional[torch.Tensor] = None) -> float:
+    """J = sum_k (u[idx_k] - obs_k)^2 and dJdu (fem_obs_misfit)."""
+    ws = _vector_workspace(idx.numel(), u.device) if workspace is None else workspace
+    J = ctypes.c_double()
+    _check(lib().fem_obs_misfit(u.numel(), idx.numel(), _ptr(idx), _ptr(obs), _ptr(u), _ptr(dJdu), ctypes.byref(J),
+                                _ptr(ws), ws.numel(), _stream()))
+    return J.value
+
+
 def _host(a, dt):
     return None if a is None else np.ascontiguousarray(a, dtype=dt)
 
@@ -227,7 +252,7 @@ class Problem:
         d = MeshDesc(prob.n_nodes, prob.n_elems, prob.ndpn, prob.model, prob.pmap, 0, prob.nu, prob.bulk_ratio,
                      prob.simp_p, prob.simp_emin, prob.simp_e0, p(k["coords"]), p(k["conn"]), p(k["mask"]),
                      p(k["f"]), p(k["src"]), 0 if k["faces"] is None else k["faces"].shape[0], p(k["faces"]),
-                     p(k["trac"]))
+                     p(k["trac"]), float(getattr(prob, "yield_stress", 0.0)))
         h = ctypes.c_void_p()
         n, nnz = ctypes.c_int64(), ctypes.c_int64()
         with torch.cuda.device(self.device):
@@ -335,6 +360,36 @@ class Problem:
         _check(lib().fem_apply_tangent(self.handle, _ptr(u), _ptr(theta), _ptr(v), _ptr(y), _ptr(ws), ws.numel(),
                                        _stream()))
         return y
+
+    def mass_apply(self, x, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """M x for a nodal field x (fem_mass_apply)."""
+        x = self._f64(x, self.n_dofs)
+        y = torch.empty_like(x) if out is None else out
+        ws = self.workspace(None)
+        _check(lib().fem_mass_apply(self.handle, _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream()))
+        return y
+
+    def set_load(self, f):
+        """Replaces the external load vector (fem_set_load)."""
+        f = self._f64(f, self.n_dofs)
+        _check(lib().fem_set_load(self.handle, _ptr(f), _stream()))
+
+    def history(self) -> torch.Tensor:
+        """The J2 history [n_elems, 8, 12] (strain then stress per Gauss point; fem_history_copy)."""
+        buf = torch.empty(self.n_elems * 96, dtype=torch.float64, device=self.device)
+        _check(lib().fem_history_copy(self.handle, _ptr(buf), 0, _stream()))
+        return buf.view(self.n_elems, 8, 12)
+
+    def set_history(self, hist):
+        """Replaces the J2 history (fem_history_copy into the handle)."""
+        h = self._f64(hist, self.n_elems * 96)
+        _check(lib().fem_history_copy(self.handle, _ptr(h), 1, _stream()))
+
+    def average_stress(self):
+        """Volume-averaged committed stress (xx, yy, zz, yz, xz, xy) (fem_average_stress)."""
+        out = (ctypes.c_double * 6)()
+        _check(lib().fem_average_stress(self.handle, out, _stream()))
+        return list(out)
 
     def param_vjp(self, u, lam, theta=None) -> torch.Tensor:
         """-lambda^T dC/dtheta per element for a given lambda (fem_param_vjp)."""
