@@ -177,6 +177,8 @@ __device__ __forceinline__ bool stopped(const KrylovScalars *sc) { return sc->co
 // Lane l of a group handles neighbour block l of each of its nodes (node degrees
 // above 32 fall back to a strided loop); the ND row sums are finished with a
 // reduce-scatter over the group (a row swap and four DPP steps, no LDS traffic).
+// Row results are kept in LDS and written (with the dot-product terms) after the
+// chunk.
 //
 // MODE 0: y = alpha K x + beta y
 // MODE 1: y = K x and alpha = rho / (w0, y)                 (BiCGSTAB v = K ph, CG q = K p)
@@ -187,26 +189,29 @@ constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
 // Nodes in flight per 32-lane group: as many as fit with the double-buffered loads
 // at an occupancy of four (FP32) or two (FP64) wavefronts per SIMD.
 template <int ND, typename T>
-constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2); }
+constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(T) == 4 ? 4 : 2); }
 
 template <int ND, int P, int MODE, typename T>
 __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                          const int32_t *__restrict__ node_nb,
                                                          const T *__restrict__ values, const T *__restrict__ x,
                                                          T *__restrict__ y, const T *__restrict__ w0, T alpha,
-                                                         T beta, double *partials, KrylovScalars *sc, int cg) {
+                                                         T beta, double *partials, KrylovScalars *sc, int cg,
+                                                         int big) {
     constexpr int G = kSpmvGroup;
     constexpr int GPB = kThreads / G;  // groups per block
     static_assert(G == 32 && (ND == 1 || ND == 3), "32-lane groups, 1 or 3 dofs per node");
     __shared__ int64_t sptr[kMaxChunk + 1];
+    __shared__ T sy[kMaxChunk * ND];  // the chunk's results, written out at its end
+    __shared__ double sdot[MODE != 0 ? 2 * kThreads : 1];  // per-thread dot terms (no registers in the node loop)
     if (MODE != 0 && stopped(sc)) return;
+    if (MODE != 0) sdot[threadIdx.x] = sdot[kThreads + threadIdx.x] = 0.0;
     int64_t r0, r1;
     block_range(Nn, r0, r1);
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     // after the group reduction, lanes 0, 8, 16 hold rows 0, 1, 2 of the node
     const int row = (lane & 7) == 0 && lane < 8 * ND ? lane / 8 : -1;
-    double d0 = 0.0, d1 = 0.0;
     for (int64_t n0 = r0; n0 < r1; n0 += kMaxChunk) {
         const int cnt = int(r1 - n0 < kMaxChunk ? r1 - n0 : kMaxChunk);
         __syncthreads();  // previous sub-chunk finished with sptr
@@ -243,13 +248,11 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
             // batch in flight (memory counters complete in issue order).
             T xm[P][ND], cv[P][ND][ND];
             int cdeg[P];
-            int64_t cb0[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
 #pragma unroll
                 for (int k = 0; k < ND; ++k) xm[p][k] = x[int64_t(ND) * m[p] + k];
                 cdeg[p] = deg[p];
-                cb0[p] = b0[p];
 #pragma unroll
                 for (int i = 0; i < ND; ++i)
 #pragma unroll
@@ -266,35 +269,61 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
                     for (int k = 0; k < ND; ++k) a += cv[p][i][k] * xm[p][k];
                     acc[i] = lane < cdeg[p] ? a : T(0);
                 }
-                for (int l = lane + G; l < cdeg[p]; l += G) {  // nodes with more than 32 neighbours
-                    const int64_t mm = node_nb[cb0[p] + l];
-                    const T *vb = values + int64_t(ND) * ND * cb0[p] + ND * l;
-#pragma unroll
-                    for (int i = 0; i < ND; ++i)
-#pragma unroll
-                        for (int k = 0; k < ND; ++k) acc[i] += vb[int64_t(i) * ND * cdeg[p] + k] * x[ND * mm + k];
-                }
                 T sv;
                 if constexpr (ND == 3) sv = group32_sum3(acc[0], acc[1], acc[2], lane);
                 else sv = group32_sum(acc[0], lane);
                 const int ln = base + p * GPB;
-                if (ln < cnt && row >= 0) {
-                    const int64_t d = int64_t(ND) * (n0 + ln) + row;
-                    if (MODE == 0) {
-                        T out = alpha * sv;
-                        if (beta != T(0)) out += beta * y[d];
-                        y[d] = out;
-                    } else {
-                        y[d] = sv;
-                        d0 += double(w0[d]) * double(sv);
-                        if (MODE == 2) d1 += double(sv) * double(sv);
-                    }
-                }
+                if (ln < cnt && row >= 0) sy[ND * ln + row] = sv;
             }
+        }
+        __syncthreads();
+        if (big) {  // neighbours beyond the 32nd of high-degree nodes (none on structured meshes)
+            for (int ln = grp; ln < cnt; ln += GPB) {
+                const int64_t b = sptr[ln];
+                const int dg = int(sptr[ln + 1] - b);
+                if (dg <= G) continue;
+                T acc[ND];
+#pragma unroll
+                for (int i = 0; i < ND; ++i) acc[i] = T(0);
+                for (int l = lane + G; l < dg; l += G) {
+                    const int64_t mm = node_nb[b + l];
+                    const T *vb = values + int64_t(ND) * ND * b + ND * l;
+#pragma unroll
+                    for (int i = 0; i < ND; ++i)
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) acc[i] += vb[int64_t(i) * ND * dg + k] * x[ND * mm + k];
+                }
+                T sv;
+                if constexpr (ND == 3) sv = group32_sum3(acc[0], acc[1], acc[2], lane);
+                else sv = group32_sum(acc[0], lane);
+                if (row >= 0) sy[ND * ln + row] += sv;
+            }
+            __syncthreads();
+        }
+        // The chunk's rows go out as one coalesced pass.  Stores share the vector
+        // memory counter with loads here, so a store inside the node loop would make
+        // every later wait for a load also wait for that store's acknowledgement.
+        double d0 = 0.0, d1 = 0.0;
+        for (int i = threadIdx.x; i < ND * cnt; i += kThreads) {
+            const int64_t d = int64_t(ND) * n0 + i;
+            const T sv = sy[i];
+            if (MODE == 0) {
+                T out = alpha * sv;
+                if (beta != T(0)) out += beta * y[d];
+                y[d] = out;
+            } else {
+                y[d] = sv;
+                d0 += double(w0[d]) * double(sv);
+                if (MODE == 2) d1 += double(sv) * double(sv);
+            }
+        }
+        if (MODE != 0) {
+            sdot[threadIdx.x] += d0;
+            sdot[kThreads + threadIdx.x] += d1;
         }
     }
     if constexpr (MODE != 0) {
-        double vv[2] = {d0, d1};
+        double vv[2] = {sdot[threadIdx.x], sdot[kThreads + threadIdx.x]};
         block_store_partials<MODE>(vv, partials);
     }
 }
@@ -916,7 +945,7 @@ static void spmv_launch(const fem_handle *h, const T *values, int transpose, con
         hipLaunchKernelGGL((k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T>),
                            dim3(resident_grid(h, k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T>)),
                            dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values, x, y, nullptr, alpha, beta,
-                           nullptr, nullptr, 0);
+                           nullptr, nullptr, 0, int(g.max_deg > kSpmvGroup));
 }
 
 #define FEM_DISPATCH_GROUP(G_RT, ND_RT, CALL)                                                      \
@@ -1016,7 +1045,8 @@ static int kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, c
     } else {
         G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T>);
         hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
-                           g.node_nb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
+                           g.node_nb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
+                           int(g.max_deg > kSpmvGroup));
     }
     if (finalize) {
         if (MODE == 1) hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kThreads), 0, s, G, k.partials, k.sc, cg);
