@@ -37,12 +37,17 @@ def log(*a):
 
 
 def spmv_bytes(prob, value_bytes):
-    """Algorithmic bytes of one fused Krylov SpMV launch: CSR values, one 32-bit column
-    index per node block, node row pointers, x gathered once, y written, one dot vector
-    read."""
+    """Algorithmic bytes of one fused Krylov SpMV launch: CSR values, one column index per
+    node block (a 16-bit offset from the row node when every neighbour lies within
+    +-32767 node numbers, which is when the library stores them so; else 32-bit), node
+    row pointers, x gathered once, y written, one dot vector read."""
     nd = prob.spec.ndpn
     n_blocks = prob.nnz // (nd * nd)
-    return prob.nnz * value_bytes + n_blocks * 4 + (prob.spec.n_nodes + 1) * 8 + 3 * prob.n_dofs * value_bytes
+    conn = prob.spec.conn
+    spread = int((conn.max(axis=1) - conn.min(axis=1)).max()) if conn.size else 0
+    idx_bytes = 2 if spread <= 32767 else 4
+    return (prob.nnz * value_bytes + n_blocks * idx_bytes + (prob.spec.n_nodes + 1) * 8
+            + 3 * prob.n_dofs * value_bytes)
 
 
 SPMV_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_nodes_nh_tensile_100x100x100.md")

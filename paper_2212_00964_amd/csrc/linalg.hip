@@ -178,7 +178,8 @@ __device__ __forceinline__ bool stopped(const KrylovScalars *sc) { return sc->co
 // above 32 fall back to a strided loop); the ND row sums are finished with a
 // reduce-scatter over the group (a row swap and four DPP steps, no LDS traffic).
 // Row results are kept in LDS and written (with the dot-product terms) after the
-// chunk.
+// chunk.  D16: column blocks read as 16-bit offsets from the row node (half the index
+// bytes) when the node numbering allows it.
 //
 // MODE 0: y = alpha K x + beta y
 // MODE 1: y = K x and alpha = rho / (w0, y)                 (BiCGSTAB v = K ph, CG q = K p)
@@ -191,9 +192,10 @@ constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
 template <int ND, typename T>
 constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(T) == 4 ? 4 : 2); }
 
-template <int ND, int P, int MODE, typename T>
+template <int ND, int P, int MODE, typename T, bool D16>
 __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                          const int32_t *__restrict__ node_nb,
+                                                         const int16_t *__restrict__ node_dnb,
                                                          const T *__restrict__ values, const T *__restrict__ x,
                                                          T *__restrict__ y, const T *__restrict__ w0, T alpha,
                                                          T beta, double *partials, KrylovScalars *sc, int cg,
@@ -232,7 +234,10 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
                 b0[p] = sptr[ln];
                 deg[p] = int(sptr[ln + 1] - b0[p]);
                 const int lc = lane < deg[p] ? lane : 0;
-                m[p] = __builtin_nontemporal_load(node_nb + b0[p] + lc);
+                if constexpr (D16)
+                    m[p] = int32_t(n0 + ln) + int32_t(__builtin_nontemporal_load(node_dnb + b0[p] + lc));
+                else
+                    m[p] = __builtin_nontemporal_load(node_nb + b0[p] + lc);
                 const T *vb = values + int64_t(ND) * ND * b0[p] + ND * lc;
 #pragma unroll
                 for (int i = 0; i < ND; ++i)
@@ -941,11 +946,16 @@ static void spmv_launch(const fem_handle *h, const T *values, int transpose, con
     if (transpose)
         hipLaunchKernelGGL((k_spmv<ND, G, true, T>), grid, dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, g.mirror,
                            values, x, y, alpha, beta);
+    else if (g.node_dnb)
+        hipLaunchKernelGGL((k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T, true>),
+                           dim3(resident_grid(h, k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T, true>)),
+                           dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, g.node_dnb, values, x, y, nullptr,
+                           alpha, beta, nullptr, nullptr, 0, int(g.max_deg > kSpmvGroup));
     else
-        hipLaunchKernelGGL((k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T>),
-                           dim3(resident_grid(h, k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T>)),
-                           dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values, x, y, nullptr, alpha, beta,
-                           nullptr, nullptr, 0, int(g.max_deg > kSpmvGroup));
+        hipLaunchKernelGGL((k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T, false>),
+                           dim3(resident_grid(h, k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T, false>)),
+                           dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, g.node_dnb, values, x, y, nullptr,
+                           alpha, beta, nullptr, nullptr, 0, int(g.max_deg > kSpmvGroup));
 }
 
 #define FEM_DISPATCH_GROUP(G_RT, ND_RT, CALL)                                                      \
@@ -1042,10 +1052,15 @@ static int kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, c
         G = resident_grid(h, k_spmv_sym<ND, P, MODE, T>);
         hipLaunchKernelGGL((k_spmv_sym<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.up_base,
                            g.node_nb, g.lo_val, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
+    } else if (g.node_dnb) {
+        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T, true>);
+        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T, true>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
+                           g.node_nb, g.node_dnb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
+                           int(g.max_deg > kSpmvGroup));
     } else {
-        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T>);
-        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
-                           g.node_nb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
+        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T, false>);
+        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T, false>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
+                           g.node_nb, g.node_dnb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
                            int(g.max_deg > kSpmvGroup));
     }
     if (finalize) {

@@ -176,6 +176,20 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     g.lo_val = upload(h, lo_val);
     g.node_ptr = upload(h, node_ptr);
     g.node_nb = upload(h, node_nb);
+    {  // 16-bit neighbour offsets for the SpMV when the numbering keeps neighbours close
+        bool fits = true;
+        std::vector<int16_t> dnb(nnzb);
+        for (int64_t n = 0; n < Nn && fits; ++n)
+            for (int64_t k = node_ptr[n]; k < node_ptr[n + 1]; ++k) {
+                const int64_t d = int64_t(node_nb[k]) - n;
+                if (d < -32768 || d > 32767) {
+                    fits = false;
+                    break;
+                }
+                dnb[k] = int16_t(d);
+            }
+        if (fits) g.node_dnb = upload(h, dnb);
+    }
     g.blk_row = upload(h, blk_row);
     g.mirror = upload(h, mirror);
     g.bdiag = upload(h, bdiag);

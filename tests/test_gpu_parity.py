@@ -168,6 +168,30 @@ def sym_to_csr(pat, sym, nd):
     return out
 
 
+def test_wide_numbering_takes_32bit_indices():
+    """Neighbour numbers more than 32767 apart (randomly relabelled 39,270-node mesh):
+    the SpMV reads 32-bit column blocks instead of 16-bit offsets.  SpMV against the
+    oracle's matrix; CG and BiCGSTAB solves checked by the oracle's residual."""
+    q, _, _ = gen.relabel(gen.cantilever(34, 33, 32), seed=5)
+    spread = (q.conn.max(axis=1) - q.conn.min(axis=1)).max()
+    assert spread > 32767
+    pat = orc.Pattern(q)
+    F = orc.load_vector(q)
+    _, K_ref = orc.assemble(q, pat, np.zeros(q.n_dofs), F=F)
+    A = pat.matrix(K_ref)
+    prob = fem.Problem(q, DEV)
+    x = np.random.default_rng(4).standard_normal(q.n_dofs)
+    for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 5e-6)):
+        _, K = prob.assemble(np.zeros(q.n_dofs), residual=False, values_dtype=dtype)
+        y = prob.spmv(K, torch.as_tensor(x, dtype=dtype, device=DEV))
+        assert rel(host(y), A @ x) <= tol
+    for kry in (fem.CG, fem.BICGSTAB):
+        u, st = prob.newton_solve(precision=fem.PREC_FP64, krylov=kry, newton_rtol=1e-11, krylov_rtol=1e-11)
+        r, _ = orc.assemble(q, pat, host(u), F=F, matrix=False)
+        assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(F), st.as_dict()
+    prob.close()
+
+
 @pytest.mark.parametrize("name", ["poisson-5x4x3-distorted", "nh-5x3x7-lognormal", "cantilever-7x3x5-distorted"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_symmetric_block_layout_assembly_and_spmv(name, dtype):
