@@ -35,7 +35,8 @@
  * must stay valid until the call's work on `stream` has finished.  The handle
  * owns its own device copies of the mesh and the sparsity structure (allocated
  * in fem_build_pattern, released by fem_destroy).  Scratch memory for assembly
- * and solves is a caller-provided device `workspace` of fem_workspace_bytes().
+ * and solves is a caller-provided device `workspace` of fem_workspace_bytes(),
+ * 256-byte aligned (FEM_EINVAL otherwise; torch allocations are).
  * `stream` is a hipStream_t passed as void* (NULL = the default stream).
  */
 #ifndef FEM_H
@@ -123,7 +124,8 @@ typedef struct {
     int32_t check_every;    /* Krylov convergence is read back every this many iterations */
     double adjoint_rtol;    /* adjoint stops when ||b - K lambda|| <= adjoint_rtol ||b|| (FP64) */
     int32_t adjoint_max_refine; /* outer refinement sweeps of the adjoint solve (mixed) */
-    int32_t profile_spmv;   /* 1: time every Krylov SpMV launch with HIP events */
+    int32_t profile_spmv;   /* 1: time the SpMV launches of the middle Krylov iteration of every
+                               check_every block with HIP events (a sample of the solve) */
     int32_t newton_fixed_its; /* > 0: run exactly this many Newton iterations per load step
                                  (the first one being the lifted step), without a convergence test */
     int32_t precond;        /* FEM_PRECOND_JACOBI or FEM_PRECOND_BLOCK_JACOBI */
@@ -138,7 +140,7 @@ typedef struct {
     double initial_residual;  /* ||r_free|| at the start of the last load step */
     double final_residual;    /* ||r_free|| (Newton) or ||b - K lambda|| (adjoint) at exit */
     double ms_residual, ms_assemble, ms_krylov, ms_vjp, ms_total;
-    int32_t spmv_calls;       /* SpMV launches timed when profile_spmv = 1 */
+    int32_t spmv_calls;       /* SpMV launches timed (sampled) when profile_spmv = 1 */
     int32_t krylov_unconverged; /* correction solves that stopped before reaching krylov_rtol */
     double spmv_ms_total;     /* their summed event durations */
     int32_t krylov_its[FEM_MAX_HIST];     /* Krylov iterations of each correction solve */

@@ -55,6 +55,7 @@ void validate_opts(const fem_solve_opts *o) {
 void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, size_t bytes) {
     size_t need = fem::solve_workspace_bytes(h, o);
     if (need > 0 && ws == nullptr) throw fem::Error(FEM_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw fem::Error(FEM_EINVAL, "workspace must be 256-byte aligned");
     if (bytes < need)
         throw fem::Error(FEM_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
 }

@@ -553,6 +553,15 @@ __global__ __launch_bounds__(kThreads) void k_fin_bicg_xr(int G, const double *_
     }
 }
 
+// 16-byte vector view of an FP32 (4 lanes) or FP64 (2 lanes) array.
+template <typename T>
+struct Vec16 {
+    static constexpr int W = 16 / int(sizeof(T));
+    typedef T type __attribute__((ext_vector_type(W)));
+    __device__ static type ld(const T *a, int64_t i) { return reinterpret_cast<const type *>(a)[i]; }
+    __device__ static void st(T *a, int64_t i, type v) { reinterpret_cast<type *>(a)[i] = v; }
+};
+
 // CG with the scalar updates folded into the vector kernels.  Each block sums the
 // previous kernel's per-block partials itself (same order in every block, so all
 // blocks agree bit for bit), which removes the one-block finalize launches.
@@ -576,7 +585,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr_fused(int64_t N, T *__restri
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->alpha = alpha;
     const T al = T(alpha);
     double d0 = 0.0, d1 = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
+    auto update = [&](int64_t i) {
         x[i] += al * p[i];
         T ri = r[i] - al * q[i];
         r[i] = ri;
@@ -584,7 +593,27 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr_fused(int64_t N, T *__restri
         z[i] = zi;
         d0 += double(ri) * double(zi);
         d1 += double(ri) * double(ri);
+    };
+    // 16-byte accesses over the bulk (the vectors are 256-byte aligned), scalar tail
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t NV = N / W;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads) {
+        typename V::type xv = V::ld(x, i), pv = V::ld(p, i), rv = V::ld(r, i), qv = V::ld(q, i), dv = V::ld(dinv, i);
+        xv += al * pv;
+        rv -= al * qv;
+        const typename V::type zv = dv * rv;
+        V::st(x, i, xv);
+        V::st(r, i, rv);
+        V::st(z, i, zv);
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            d0 += double(rv[c]) * double(zv[c]);
+            d1 += double(rv[c]) * double(rv[c]);
+        }
     }
+    if (blockIdx.x == 0)
+        for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) update(i);
     double v[2] = {d0, d1};
     block_store_partials<2>(v, partials);
 }
@@ -614,8 +643,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_p_fused(int64_t N, const T *__r
     }
     if (nan || conv) return;
     const T bt = T(beta);
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
-        p[i] = z[i] + bt * p[i];
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t NV = N / W;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads)
+        V::st(p, i, V::ld(z, i) + bt * V::ld(p, i));
+    if (blockIdx.x == 0)
+        for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) p[i] = z[i] + bt * p[i];
 }
 
 // ------------------------------------------------------------------ block Jacobi variants

@@ -149,31 +149,32 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
     const int spmv_per_it = cg ? 1 : 2;
     std::vector<hipEvent_t> &ev = h->events;
     const bool prof = o.profile_spmv != 0;
-    if (prof && ev.size() < size_t(4 * every)) {
+    if (prof && ev.size() < 4) {
         size_t old = ev.size();
-        ev.resize(4 * every);
+        ev.resize(4);
         for (size_t i = old; i < ev.size(); ++i) FEM_HIP(hipEventCreate(&ev[i]));
     }
     int its_done = 0;
     KrylovScalars hs{};
     for (int it = 0;; it += every) {
         for (int j = 0; j < every; ++j) {
-            hipEvent_t *e = prof ? &ev[4 * j] : nullptr;
+            // timing samples the middle iteration of each check interval (away from the
+            // host read-back at its end): an event pair around every SpMV would itself
+            // cost about 4% of the iteration time
+            hipEvent_t *e = (prof && j == every / 2) ? &ev[0] : nullptr;
             if (cg) kry_cg_iter<T>(h, k, it + j, s, e);
             else kry_bicg_iter<T>(h, k, s, e);
         }
         FEM_HIP(hipMemcpyAsync(h->host_kry, w.sc, kScalarsHostBytes, hipMemcpyDeviceToHost, s));
         FEM_HIP(hipStreamSynchronize(s));
         std::memcpy(&hs, h->host_kry, kScalarsHostBytes);
-        if (prof && st) {
-            int ran = hs.its - its_done;
-            for (int j = 0; j < ran && j < every; ++j)
-                for (int q = 0; q < spmv_per_it; ++q) {
-                    float ms = 0.f;
-                    FEM_HIP(hipEventElapsedTime(&ms, ev[4 * j + 2 * q], ev[4 * j + 2 * q + 1]));
-                    st->spmv_ms_total += ms;
-                    st->spmv_calls += 1;
-                }
+        if (prof && st && hs.its > its_done + every / 2) {  // the sampled iteration did an update
+            for (int q = 0; q < spmv_per_it; ++q) {
+                float ms = 0.f;
+                FEM_HIP(hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
+                st->spmv_ms_total += ms;
+                st->spmv_calls += 1;
+            }
         }
         its_done = hs.its;
         if (hs.converged) break;
