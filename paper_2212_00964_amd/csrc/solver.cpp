@@ -343,7 +343,10 @@ static void adjoint_impl(fem_handle *h, const double *u, const double *theta, co
         if (sweeps >= o.adjoint_max_refine) throw Error(FEM_EMAXITER, "adjoint refinement did not converge");
         t0 = clk::now();
         launch_scale_cast<T, double>(w.res64, static_cast<T *>(w.b), 1.0, N, s);
-        int kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, o.krylov_rtol, st, s);
+        // Each sweep asks only for what is still missing, with a factor 2 of margin for
+        // the gap between the recursive and the true residual.
+        const double eta = std::min(0.5, std::max(o.krylov_rtol, 0.5 * tol / rn));
+        int kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, eta, st, s);
         launch_axpy_to_f64<T>(static_cast<const T *>(w.x), w.lam64, N, s);
         if (st) {
             st->ms_krylov += ms_since(t0);
