@@ -561,6 +561,7 @@ struct Vec16 {
     typedef T type __attribute__((ext_vector_type(W)));
     __device__ static type ld(const T *a, int64_t i) { return reinterpret_cast<const type *>(a)[i]; }
     __device__ static void st(T *a, int64_t i, type v) { reinterpret_cast<type *>(a)[i] = v; }
+    __device__ static void st_nt(T *a, int64_t i, type v) { __builtin_nontemporal_store(v, reinterpret_cast<type *>(a) + i); }
 };
 
 // CG with the scalar updates folded into the vector kernels.  Each block sums the
@@ -604,9 +605,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr_fused(int64_t N, T *__restri
         xv += al * pv;
         rv -= al * qv;
         const typename V::type zv = dv * rv;
-        V::st(x, i, xv);
-        V::st(r, i, rv);
-        V::st(z, i, zv);
+        V::st_nt(x, i, xv);
+        V::st_nt(r, i, rv);
+        V::st_nt(z, i, zv);
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             d0 += double(rv[c]) * double(zv[c]);
@@ -648,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_p_fused(int64_t N, const T *__r
     constexpr int W = V::W;
     const int64_t NV = N / W;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads)
-        V::st(p, i, V::ld(z, i) + bt * V::ld(p, i));
+        V::st_nt(p, i, V::ld(z, i) + bt * V::ld(p, i));
     if (blockIdx.x == 0)
         for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) p[i] = z[i] + bt * p[i];
 }
