@@ -82,8 +82,16 @@ enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
 enum { FEM_KRYLOV_CG = 0, FEM_KRYLOV_BICGSTAB = 1 };
 /* Krylov preconditioner.  FEM_PRECOND_JACOBI: the inverse diagonal of the tangent
  * (the paper's Jacobi preconditioner, Sec. 5).  FEM_PRECOND_BLOCK_JACOBI: the
- * inverse of each node's ndpn x ndpn diagonal block (equal to Jacobi when ndpn = 1). */
-enum { FEM_PRECOND_JACOBI = 0, FEM_PRECOND_BLOCK_JACOBI = 1 };
+ * inverse of each node's ndpn x ndpn diagonal block (equal to Jacobi when ndpn = 1).
+ * FEM_PRECOND_AMG (CG only): a two-level aggregation preconditioner, one symmetric
+ * V-cycle per application -- Chebyshev smoothing of the Jacobi-scaled tangent, a
+ * Galerkin coarse operator on a rigid-body-mode coarse space of node aggregates (6
+ * columns per aggregate; 1, the constant, when ndpn = 1) and Chebyshev steps on it.
+ * The paper names the Jacobi-preconditioned solver as the bottleneck (Sec. 5, item 2);
+ * this is the stronger preconditioner built on that remark.  The handle builds the
+ * aggregates and prolongator once (first use) and keeps them with the coarse operator
+ * of the latest tangent; see fem_amg_export / fem_amg_apply below. */
+enum { FEM_PRECOND_JACOBI = 0, FEM_PRECOND_BLOCK_JACOBI = 1, FEM_PRECOND_AMG = 2 };
 
 typedef struct fem_handle fem_handle;
 
@@ -128,7 +136,9 @@ typedef struct {
                                check_every block with HIP events (a sample of the solve) */
     int32_t newton_fixed_its; /* > 0: run exactly this many Newton iterations per load step
                                  (the first one being the lifted step), without a convergence test */
-    int32_t precond;        /* FEM_PRECOND_JACOBI or FEM_PRECOND_BLOCK_JACOBI */
+    int32_t precond;        /* FEM_PRECOND_JACOBI, FEM_PRECOND_BLOCK_JACOBI or FEM_PRECOND_AMG (CG only) */
+    int32_t amg_smooth_degree; /* FEM_PRECOND_AMG: Chebyshev steps of each fine smoothing (1..64) */
+    int32_t amg_coarse_degree; /* FEM_PRECOND_AMG: Chebyshev steps on the coarse operator (1..64) */
 } fem_solve_opts;
 
 #define FEM_MAX_HIST 64
@@ -255,6 +265,32 @@ int fem_history_copy(fem_handle *h, double *buf, int32_t into_handle, void *stre
  * for its loading-unloading path; zeros for an empty mesh).  Blocks.  FEM_EINVAL for
  * other laws. */
 int fem_average_stress(fem_handle *h, double *out, void *stream);
+
+/* ------------------------------------------------------------------------------
+ * Two-level preconditioner (FEM_PRECOND_AMG): its parts, for inspection and tests.
+ * ---------------------------------------------------------------------------- */
+
+/* Builds the aggregation and prolongator if needed and returns, to the host, the
+ * number of aggregates and of coarse ncoarse x ncoarse blocks (ncoarse = 6, or 1 when
+ * ndpn = 1).  Synchronous. */
+int fem_amg_sizes(fem_handle *h, int64_t *n_aggregates, int64_t *n_coarse_blocks);
+
+/* Copies to caller DEVICE buffers (any may be NULL): the aggregate of every node
+ * agg [n_nodes] int32; the prolongator P [n_nodes * ndpn * ncoarse] FP64, row-major
+ * ndpn x ncoarse per node (rows of Dirichlet dofs and dropped columns are zero); the
+ * coarse block pattern coarse_ptr [n_aggregates + 1] int64 and coarse_col
+ * [n_coarse_blocks] int32 (aggregates ascending per row).  Synchronous. */
+int fem_amg_export(fem_handle *h, int32_t *agg, double *P, int64_t *coarse_ptr, int32_t *coarse_col);
+
+/* Assembles the tangent at (u, theta) in opts->precision, builds the coarse operator
+ * and the Chebyshev intervals, and applies the preconditioner once: z = M r (r, z
+ * [N] FP64 device, distinct).  lmax_out (host, may be NULL) receives the fine and
+ * coarse largest-eigenvalue bounds; coarse_values (device, may be NULL) receives the
+ * coarse operator, FP64 [n_coarse_blocks * ncoarse^2] block-major row-major.  Uses the
+ * solve workspace of fem_workspace_bytes(opts).  Synchronous. */
+int fem_amg_apply(fem_handle *h, const double *u, const double *theta, const double *r, double *z,
+                  const fem_solve_opts *opts, double *lmax_out, double *coarse_values, void *workspace,
+                  size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------
  * SIMP compliance optimisation (Sec. 4.2): the pieces around the gradient.  The

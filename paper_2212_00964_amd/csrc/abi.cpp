@@ -49,7 +49,14 @@ void validate_opts(const fem_solve_opts *o) {
     require(o->newton_rtol >= 0.0 && o->newton_atol >= 0.0 && o->adjoint_rtol >= 0.0, "opts tolerances");
     require(o->adjoint_max_refine >= 1, "opts.adjoint_max_refine must be >= 1");
     require(o->newton_fixed_its >= 0, "opts.newton_fixed_its must be >= 0");
-    require(o->precond == FEM_PRECOND_JACOBI || o->precond == FEM_PRECOND_BLOCK_JACOBI, "opts.precond");
+    require(o->precond == FEM_PRECOND_JACOBI || o->precond == FEM_PRECOND_BLOCK_JACOBI ||
+                o->precond == FEM_PRECOND_AMG,
+            "opts.precond");
+    if (o->precond == FEM_PRECOND_AMG) {
+        require(o->krylov == FEM_KRYLOV_CG, "FEM_PRECOND_AMG needs FEM_KRYLOV_CG");
+        require(o->amg_smooth_degree >= 1 && o->amg_smooth_degree <= 64, "opts.amg_smooth_degree must be in [1, 64]");
+        require(o->amg_coarse_degree >= 1 && o->amg_coarse_degree <= 64, "opts.amg_coarse_degree must be in [1, 64]");
+    }
 }
 
 void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, size_t bytes) {
@@ -82,6 +89,8 @@ int fem_default_opts(fem_solve_opts *o) {
         o->adjoint_rtol = 1e-10;
         o->adjoint_max_refine = 20;
         o->profile_spmv = 0;
+        o->amg_smooth_degree = 2;
+        o->amg_coarse_degree = 16;
         o->newton_fixed_its = 0;
         o->precond = FEM_PRECOND_JACOBI;
     });
@@ -162,6 +171,7 @@ void fem_destroy(fem_handle *h) {
     if (h->host_status) (void)hipHostFree(h->host_status);
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);
     if (h->host_kry) (void)hipHostFree(h->host_kry);
+    fem::amg_destroy(h);
     delete h;
 }
 
@@ -326,6 +336,48 @@ int fem_average_stress(fem_handle *h, double *out, void *stream) {
         require(h->mat.model == FEM_J2_PLASTIC, "the handle's law has no history (FEM_J2_PLASTIC only)");
         bind_device(h);
         fem::j2_average_stress(h, out, as_stream(stream));
+    });
+}
+
+int fem_amg_sizes(fem_handle *h, int64_t *n_aggregates, int64_t *n_coarse_blocks) {
+    return guarded([&] {
+        require(h != nullptr && n_aggregates != nullptr && n_coarse_blocks != nullptr, "arguments must be non-NULL");
+        bind_device(h);
+        fem::amg_setup(h);
+        *n_aggregates = h->amg->na;
+        *n_coarse_blocks = h->amg->nbc;
+    });
+}
+
+int fem_amg_export(fem_handle *h, int32_t *agg, double *P, int64_t *coarse_ptr, int32_t *coarse_col) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        bind_device(h);
+        fem::amg_setup(h);
+        const fem::Amg &a = *h->amg;
+        const int64_t Nn = h->g.Nn;
+        if (agg && Nn) FEM_HIP(hipMemcpy(agg, a.agg, Nn * sizeof(int32_t), hipMemcpyDeviceToDevice));
+        if (P && Nn)
+            FEM_HIP(hipMemcpy(P, a.P64, size_t(Nn) * h->g.nd * a.nc * sizeof(double), hipMemcpyDeviceToDevice));
+        if (coarse_ptr) FEM_HIP(hipMemcpy(coarse_ptr, a.cptr, (a.na + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice));
+        if (coarse_col && a.nbc)
+            FEM_HIP(hipMemcpy(coarse_col, a.ccol, a.nbc * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    });
+}
+
+int fem_amg_apply(fem_handle *h, const double *u, const double *theta, const double *r, double *z,
+                  const fem_solve_opts *opts, double *lmax_out, double *coarse_values, void *workspace,
+                  size_t workspace_bytes, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        validate_opts(opts);
+        require(opts->precond == FEM_PRECOND_AMG, "opts.precond must be FEM_PRECOND_AMG");
+        if (h->g.N == 0) return;
+        require(u && theta && r && z && r != z, "u, theta, r and z must be non-NULL (r and z distinct)");
+        check_workspace(h, opts, workspace, workspace_bytes);
+        bind_device(h);
+        fem::amg_apply_once(h, u, theta, r, z, *opts, lmax_out, coarse_values, workspace, workspace_bytes,
+                            as_stream(stream));
     });
 }
 

@@ -104,6 +104,34 @@ struct Filter {
     std::vector<void *> allocations;
 };
 
+// Two-level aggregation preconditioner (amg.hip).  Built once per handle (first use);
+// the coarse operator and the Chebyshev bounds are refreshed for every tangent.
+struct Amg {
+    int64_t na = 0, nbc = 0;       // aggregates, coarse blocks
+    int nc = 0;                    // coarse dofs per aggregate (6, or 1 when ndpn = 1)
+    int32_t *agg = nullptr;        // [Nn] aggregate of each node
+    int64_t *agg_ptr = nullptr;    // [na+1] members of each aggregate in agg_nodes
+    int32_t *agg_nodes = nullptr;  // [Nn] nodes ascending per aggregate
+    double *P64 = nullptr;         // [Nn*nd*nc] prolongator, row-major nd x nc per node
+    float *P32 = nullptr;          // the same in FP32
+    int64_t *cptr = nullptr;       // [na+1] coarse block rows
+    int32_t *ccol = nullptr;       // [nbc] column aggregate of each coarse block
+    int32_t *crow = nullptr;       // [nbc] row aggregate of each coarse block
+    int64_t *cdiag = nullptr;      // [na] diagonal block of each row
+    int64_t *cbp = nullptr;        // [nbc+1] fine blocks feeding each coarse block in cbk
+    int32_t *cbk = nullptr;        // [nnzb] fine block indices, ascending per coarse block
+    uint8_t *dropped = nullptr;    // [na] bit k set: coarse column k of the aggregate is empty
+    void *cvals = nullptr;         // [nbc*nc*nc] coarse operator in the solve precision
+    void *cdinv = nullptr;         // [na*nc] its inverse diagonal
+    void *fine_tmp = nullptr;      // 3 fine vectors [N] (SpMV output, Chebyshev residual, direction)
+    void *coarse_tmp = nullptr;    // 5 coarse vectors [na*nc]
+    double *red = nullptr;         // reduction partials
+    double *host_red = nullptr;    // pinned read-back of the partials
+    double lmax = 0.0, lmax_c = 0.0;
+    int precision = -1;            // precision of the current coarse operator
+    int sdeg = 2, cdeg = 16;       // Chebyshev degrees of the smoother and of the coarse solve
+};
+
 }  // namespace fem
 
 struct fem_handle {
@@ -123,6 +151,7 @@ struct fem_handle {
     double *red_partials = nullptr;           // reduction partials of fem_element_volumes (lazy)
     double *hist = nullptr;                   // J2 history [Ne*8*12] (eps, sigma per Gauss point)
     double *hist_partials = nullptr;          // per-block partials of fem_average_stress (lazy)
+    fem::Amg *amg = nullptr;                  // two-level preconditioner (lazy)
 };
 
 namespace fem {
@@ -189,6 +218,31 @@ template <typename T>
 void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
 template <typename T>
 void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
+// Two-level preconditioned CG (amg.hip): init (z = M b) and iteration `it`.
+template <typename T>
+void kry_cg_amg_init(fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
+template <typename T>
+void kry_cg_amg_iter(fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev);
+// Builds the aggregation (once) and the coarse operator and bounds for `values`.
+void amg_setup(fem_handle *h);
+template <typename T>
+void amg_refresh(fem_handle *h, const T *values, const T *dinv, int precision, int smooth_degree, int coarse_degree,
+                 hipStream_t s);
+// z = M r in the solve precision (no convergence flag).
+template <typename T>
+void amg_apply(fem_handle *h, const T *values, const T *dinv, const T *r, T *z, const KrylovScalars *sc,
+               hipStream_t s);
+void amg_destroy(fem_handle *h);
+void amg_coarse_values_f64(const fem_handle *h, double *out, hipStream_t s);
+// CG kernels shared with the preconditioned iteration (linalg.hip).
+int krylov_vec_grid_of(const fem_handle *h);
+template <typename T>
+int kry_spmv_q(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s);  // q = K p, (p, q) partials
+template <typename T>
+void kry_cg_p_update(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s);
+template <typename T>
+void launch_spmv_sc(const fem_handle *h, const T *values, const T *x, T *y, T alpha, T beta, const KrylovScalars *sc,
+                    hipStream_t s);
 // CG iteration number `it` (0-based within this solve).
 template <typename T>
 void kry_cg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev);

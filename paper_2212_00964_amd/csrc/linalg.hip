@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
     __shared__ int64_t sptr[kMaxChunk + 1];
     __shared__ T sy[kMaxChunk * ND];  // the chunk's results, written out at its end
     __shared__ double sdot[MODE != 0 ? 2 * kThreads : 1];  // per-thread dot terms (no registers in the node loop)
-    if (MODE != 0 && stopped(sc)) return;
+    if ((MODE != 0 || sc != nullptr) && stopped(sc)) return;  // MODE 0 with sc: inside a Krylov loop
     if (MODE != 0) sdot[threadIdx.x] = sdot[kThreads + threadIdx.x] = 0.0;
     int64_t r0, r1;
     block_range(Nn, r0, r1);
@@ -1114,6 +1114,44 @@ static int kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const Kr
 }
 
 template <typename T>
+int kry_spmv_q(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s) {
+    return kry_spmv<T, 1>(h, k.p, k.v, k.p, k, 1, k.A, s, false);
+}
+
+int krylov_vec_grid_of(const fem_handle *h) { return krylov_vec_grid(h); }
+
+// p = z + beta p from the (r, z) and |r|^2 partials in k.partials2 (krylov_vec_grid of them).
+template <typename T>
+void kry_cg_p_update(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s) {
+    const int G = krylov_vec_grid(h);
+    hipLaunchKernelGGL((k_cg_p_fused<T>), dim3(G), dim3(kThreads), 0, s, h->g.N, k.rh, k.p, k.partials2, G, k.sc, it);
+    FEM_HIP(hipGetLastError());
+}
+
+// y = alpha K x + beta y inside a Krylov loop: skipped once sc reports convergence.
+template <typename T>
+void launch_spmv_sc(const fem_handle *h, const T *values, const T *x, T *y, T alpha, T beta, const KrylovScalars *sc,
+                    hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.N == 0) return;
+    KrylovScalars *scw = const_cast<KrylovScalars *>(sc);
+#define FEM_SPMV_SC(ND, D16)                                                                                       \
+    hipLaunchKernelGGL((k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T, D16>),                                         \
+                       dim3(resident_grid(h, k_spmv_nodes<ND, spmv_batch<ND, T>(), 0, T, D16>)), dim3(kThreads), 0, \
+                       s, g.Nn, g.node_ptr, g.node_nb, g.node_dnb, values, x, y, nullptr, alpha, beta, nullptr,   \
+                       scw, 0, int(g.max_deg > kSpmvGroup))
+    if (g.nd == 1) {
+        if (g.node_dnb) FEM_SPMV_SC(1, true);
+        else FEM_SPMV_SC(1, false);
+    } else {
+        if (g.node_dnb) FEM_SPMV_SC(3, true);
+        else FEM_SPMV_SC(3, false);
+    }
+#undef FEM_SPMV_SC
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
 void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev) {
     const int64_t N = h->g.N;
     dim3 grid(krylov_grid(h)), blk(kThreads);
@@ -1169,6 +1207,14 @@ template void kry_cg_init<float>(const fem_handle *, const KrylovVecs<float> &, 
 template void kry_cg_init<double>(const fem_handle *, const KrylovVecs<double> &, const double *, double, hipStream_t);
 template void kry_bicg_iter<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t, hipEvent_t *);
 template void kry_bicg_iter<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t, hipEvent_t *);
+template int kry_spmv_q<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t);
+template int kry_spmv_q<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t);
+template void kry_cg_p_update<float>(const fem_handle *, const KrylovVecs<float> &, int, hipStream_t);
+template void kry_cg_p_update<double>(const fem_handle *, const KrylovVecs<double> &, int, hipStream_t);
+template void launch_spmv_sc<float>(const fem_handle *, const float *, const float *, float *, float, float,
+                                    const KrylovScalars *, hipStream_t);
+template void launch_spmv_sc<double>(const fem_handle *, const double *, const double *, double *, double, double,
+                                     const KrylovScalars *, hipStream_t);
 template void kry_cg_iter<float>(const fem_handle *, const KrylovVecs<float> &, int, hipStream_t, hipEvent_t *);
 template void kry_cg_iter<double>(const fem_handle *, const KrylovVecs<double> &, int, hipStream_t, hipEvent_t *);
 template void launch_spmv<float>(const fem_handle *, const float *, int, const float *, float *, float, float,

@@ -142,10 +142,13 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
                     w.partials2,
                     w.sc};
     const bool cg = o.krylov == FEM_KRYLOV_CG;
+    const bool amg = o.precond == FEM_PRECOND_AMG;  // CG only (checked at the ABI)
     const T *b = static_cast<const T *>(w.b);
-    if (cg) kry_cg_init<T>(h, k, b, rtol, s);
+    if (amg) kry_cg_amg_init<T>(h, k, b, rtol, s);
+    else if (cg) kry_cg_init<T>(h, k, b, rtol, s);
     else kry_bicg_init<T>(h, k, b, rtol, s);
-    const int every = std::max(1, o.check_every);
+    // a two-level iteration costs several SpMVs: read convergence back more often
+    const int every = amg ? std::max(1, std::min(o.check_every, 4)) : std::max(1, o.check_every);
     const int spmv_per_it = cg ? 1 : 2;
     std::vector<hipEvent_t> &ev = h->events;
     const bool prof = o.profile_spmv != 0;
@@ -162,7 +165,8 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
             // host read-back at its end): an event pair around every SpMV would itself
             // cost about 4% of the iteration time
             hipEvent_t *e = (prof && j == every / 2) ? &ev[0] : nullptr;
-            if (cg) kry_cg_iter<T>(h, k, it + j, s, e);
+            if (amg) kry_cg_amg_iter<T>(h, k, it + j, s, e);
+            else if (cg) kry_cg_iter<T>(h, k, it + j, s, e);
             else kry_bicg_iter<T>(h, k, s, e);
         }
         FEM_HIP(hipMemcpyAsync(h->host_kry, w.sc, kScalarsHostBytes, hipMemcpyDeviceToHost, s));
@@ -211,10 +215,13 @@ static double ms_since(clk::time_point t0) {
 }
 
 template <typename T>
-static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const double *theta, int precond,
-                          hipStream_t s) {
+static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const double *theta,
+                          const fem_solve_opts &o, hipStream_t s) {
     launch_tangent<T>(h, u, theta, static_cast<T *>(w.ke), static_cast<T *>(w.values), static_cast<T *>(w.dinv), s,
-                      kSolverLayout, precond);
+                      kSolverLayout, o.precond);
+    if (o.precond == FEM_PRECOND_AMG)  // the coarse operator and bounds of this tangent
+        amg_refresh<T>(h, static_cast<const T *>(w.values), static_cast<const T *>(w.dinv), o.precision,
+                       o.amg_smooth_degree, o.amg_coarse_degree, s);
 }
 
 // One correction: assemble K(u), solve K du = b (b already in w.b), u += du.
@@ -223,7 +230,7 @@ static int correction(fem_handle *h, SolveWork &w, double *u, const double *thet
                       fem_solve_stats *st, double rn, hipStream_t s) {
     const int64_t N = h->g.N;
     auto t0 = clk::now();
-    assemble_into<T>(h, w, u, theta, o.precond, s);
+    assemble_into<T>(h, w, u, theta, o, s);
     check_status(h, s);
     if (st) st->ms_assemble += ms_since(t0);
     t0 = clk::now();
@@ -328,7 +335,7 @@ static void adjoint_impl(fem_handle *h, const double *u, const double *theta, co
     auto t0 = clk::now();
     // All laws here have major-symmetric tangents and the Dirichlet elimination is
     // symmetric, so (dC/du)^T is the assembled K itself.
-    assemble_into<T>(h, w, u, theta, o.precond, s);
+    assemble_into<T>(h, w, u, theta, o, s);
     launch_mask_copy(h, dJdu, w.res64, s);  // b = dJ/du with Dirichlet entries 0
     double bn = norm2(h, w.res64, w, s);
     check_status(h, s);
@@ -377,6 +384,38 @@ static void adjoint_impl(fem_handle *h, const double *u, const double *theta, co
         st->newton_its += sweeps;
         st->ms_total += ms_since(t_all);
     }
+}
+
+template <typename T>
+static void amg_apply_impl(fem_handle *h, const double *u, const double *theta, const double *r, double *z,
+                           const fem_solve_opts &o, double *lmax_out, double *coarse_values, void *ws, size_t wsb,
+                           hipStream_t s) {
+    Carver c(ws, wsb, false);
+    SolveWork w;
+    carve_solve<T>(c, h, w, true);
+    const int64_t N = h->g.N;
+    reset_status(h, s);
+    assemble_into<T>(h, w, u, theta, o, s);
+    check_status(h, s);
+    launch_scale_cast<T, double>(r, static_cast<T *>(w.b), 1.0, N, s);
+    amg_apply<T>(h, static_cast<const T *>(w.values), static_cast<const T *>(w.dinv), static_cast<const T *>(w.b),
+                 static_cast<T *>(w.x), nullptr, s);
+    FEM_HIP(hipMemsetAsync(z, 0, N * sizeof(double), s));
+    launch_axpy_to_f64<T>(static_cast<const T *>(w.x), z, N, s);
+    if (coarse_values) amg_coarse_values_f64(h, coarse_values, s);
+    FEM_HIP(hipStreamSynchronize(s));
+    if (lmax_out) {
+        lmax_out[0] = h->amg->lmax;
+        lmax_out[1] = h->amg->lmax_c;
+    }
+}
+
+void amg_apply_once(fem_handle *h, const double *u, const double *theta, const double *r, double *z,
+                    const fem_solve_opts &o, double *lmax_out, double *coarse_values, void *ws, size_t wsb,
+                    hipStream_t s) {
+    if (o.precision == FEM_PREC_MIXED)
+        amg_apply_impl<float>(h, u, theta, r, z, o, lmax_out, coarse_values, ws, wsb, s);
+    else amg_apply_impl<double>(h, u, theta, r, z, o, lmax_out, coarse_values, ws, wsb, s);
 }
 
 void adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *g,

@@ -27,5 +27,9 @@ void newton_solve(fem_handle *h, double *u, const double *theta, const double *g
                   fem_solve_stats *st, void *ws, size_t wsb, hipStream_t s);
 void adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *g, double *lam_out,
                  const fem_solve_opts &o, fem_solve_stats *st, void *ws, size_t wsb, hipStream_t s);
+// Assembles K(u), builds the two-level preconditioner for it and applies it once.
+void amg_apply_once(fem_handle *h, const double *u, const double *theta, const double *r, double *z,
+                    const fem_solve_opts &o, double *lmax_out, double *coarse_values, void *ws, size_t wsb,
+                    hipStream_t s);
 
 }  // namespace fem

@@ -25,7 +25,7 @@ F32, F64 = 0, 1
 LAYOUT_CSR, LAYOUT_SYM_BLOCK = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 CG, BICGSTAB = 0, 1
-PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1
+PRECOND_JACOBI, PRECOND_BLOCK_JACOBI, PRECOND_AMG = 0, 1, 2
 FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
 MAX_HIST = 64
 
@@ -57,7 +57,8 @@ class SolveOpts(ctypes.Structure):
                 ("newton_atol", ctypes.c_double), ("krylov_rtol", ctypes.c_double),
                 ("krylov_max_it", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("adjoint_rtol", ctypes.c_double), ("adjoint_max_refine", ctypes.c_int32),
-                ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("amg_smooth_degree", ctypes.c_int32), ("amg_coarse_degree", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -88,7 +89,7 @@ class MmaOpts(ctypes.Structure):
 EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
            "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv",
            "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_history_copy", "fem_average_stress",
-           "fem_param_vjp", "fem_element_volumes",
+           "fem_amg_sizes", "fem_amg_export", "fem_amg_apply", "fem_param_vjp", "fem_element_volumes",
            "fem_filter_setup", "fem_filter_apply", "fem_vector_workspace_bytes", "fem_dot", "fem_mma_default_opts",
            "fem_mma_update", "fem_mass_apply", "fem_set_load", "fem_axpby", "fem_obs_misfit"]
 
@@ -125,6 +126,9 @@ def lib():
         "fem_adjoint_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
         "fem_history_copy": (ctypes.c_int, [vp, vp, i32, vp]),
         "fem_average_stress": (ctypes.c_int, [vp, P(dbl), vp]),
+        "fem_amg_sizes": (ctypes.c_int, [vp, P(i64), P(i64)]),
+        "fem_amg_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fem_amg_apply": (ctypes.c_int, [vp, vp, vp, vp, vp, P(SolveOpts), P(dbl), vp, vp, sz, vp]),
         "fem_param_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "fem_element_volumes": (ctypes.c_int, [vp, vp, i32, vp]),
         "fem_filter_setup": (ctypes.c_int, [vp, dbl]),
@@ -390,6 +394,46 @@ class Problem:
         out = (ctypes.c_double * 6)()
         _check(lib().fem_average_stress(self.handle, out, _stream()))
         return list(out)
+
+    def amg_sizes(self):
+        """(aggregates, coarse blocks) of the two-level preconditioner (fem_amg_sizes)."""
+        na, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fem_amg_sizes(self.handle, ctypes.byref(na), ctypes.byref(nb)))
+        return na.value, nb.value
+
+    def amg_export(self) -> dict:
+        """Aggregates, prolongator and coarse block pattern (fem_amg_export)."""
+        na, nb = self.amg_sizes()
+        nc = 6 if self.spec.ndpn == 3 else 1
+        dev = self.device
+        out = {"agg": torch.empty(self.spec.n_nodes, dtype=torch.int32, device=dev),
+               "P": torch.empty(self.n_dofs * nc, dtype=torch.float64, device=dev),
+               "coarse_ptr": torch.empty(na + 1, dtype=torch.int64, device=dev),
+               "coarse_col": torch.empty(max(nb, 1), dtype=torch.int32, device=dev)}
+        _check(lib().fem_amg_export(self.handle, _ptr(out["agg"]), _ptr(out["P"]), _ptr(out["coarse_ptr"]),
+                                    _ptr(out["coarse_col"])))
+        out["coarse_col"] = out["coarse_col"][:nb]
+        out["n_aggregates"], out["n_coarse_blocks"], out["nc"] = na, nb, nc
+        return out
+
+    def amg_apply(self, u, r, theta=None, opts: Optional[SolveOpts] = None, **kw):
+        """z = M r with the two-level preconditioner of K(u) (fem_amg_apply); returns
+        (z, [lmax fine, lmax coarse], coarse operator values FP64)."""
+        kw.setdefault("precond", PRECOND_AMG)
+        kw.setdefault("krylov", CG)
+        opts = self.opts(**kw) if opts is None else opts
+        u = self._f64(u, self.n_dofs)
+        r = self._f64(r, self.n_dofs)
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        na, nb = self.amg_sizes()
+        nc = 6 if self.spec.ndpn == 3 else 1
+        z = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        cv = torch.empty(max(nb * nc * nc, 1), dtype=torch.float64, device=self.device)
+        lm = (ctypes.c_double * 2)()
+        ws = self.workspace(opts)
+        _check(lib().fem_amg_apply(self.handle, _ptr(u), _ptr(theta), _ptr(r), _ptr(z), ctypes.byref(opts), lm,
+                                   _ptr(cv), _ptr(ws), ws.numel(), _stream()))
+        return z, list(lm), cv[:nb * nc * nc]
 
     def param_vjp(self, u, lam, theta=None) -> torch.Tensor:
         """-lambda^T dC/dtheta per element for a given lambda (fem_param_vjp)."""
