@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--size", type=int, nargs=3, default=[100, 100, 100])
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--krylov", choices=["cg", "bicgstab"], default="cg")
+    ap.add_argument("--precond", choices=["jacobi", "block-jacobi", "two-level"], default="jacobi",
+                    help="preconditioner of the timed step (the paper's Jacobi by default)")
     ap.add_argument("--krylov-rtol", type=float, default=1e-3)
     ap.add_argument("--adjoint-rtol", type=float, default=1e-5,
                     help="relative FP64 residual of the adjoint solve; 1e-5 keeps the gradient within ~1e-7 of "
@@ -213,10 +215,12 @@ def main():
     log(f"load step 5: newton_its={st5.newton_its} krylov_its={list(st5.krylov_its[:st5.n_hist])}")
     dJdu = torch.where(prob.mask, torch.zeros_like(u5), u5)
 
+    pc = {"jacobi": fem.PRECOND_JACOBI, "block-jacobi": fem.PRECOND_BLOCK_JACOBI,
+          "two-level": fem.PRECOND_AMG}[args.precond]
     step_opts = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_fixed_its=1,
-                          krylov_rtol=args.krylov_rtol, profile_spmv=1)
+                          krylov_rtol=args.krylov_rtol, profile_spmv=1, precond=pc)
     adj_opts = prob.opts(precision=prec, krylov=kry, krylov_rtol=args.krylov_rtol, adjoint_rtol=args.adjoint_rtol,
-                         profile_spmv=1)
+                         profile_spmv=1, precond=pc)
 
     def step():
         u, sn = prob.newton_solve(u0=u4, opts=step_opts)
@@ -256,7 +260,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"neo-Hookean tensile block {nx}x{ny}x{nz} HEX8 ({p.n_elems} elements, "
                                f"{p.n_dofs} dofs, nnz {prob.nnz}), lognormal G (ln 10, 0.3), kappa = 10 G, "
-                               f"load step 5 of 5 to stretch 1.2; Jacobi-{args.krylov} (inner rtol "
+                               f"load step 5 of 5 to stretch 1.2; {args.precond}-{args.krylov} (inner rtol "
                                f"{args.krylov_rtol:g}), adjoint rtol {args.adjoint_rtol:g}",
                    "precision": args.precision, "parallelism": "single GPU"},
         "newton_step_ms": t_newton, "adjoint_grad_ms": t_adj,
@@ -309,14 +313,36 @@ def main():
             "grad_rel_err_vs_fp64_ref": float(torch.linalg.norm(g_b - g_ref) / torch.linalg.norm(g_ref))}
         log(f"block-Jacobi step: newton {sb.ms_total:.1f} ms ({sb.krylov_its_total} its), adjoint {sba.ms_total:.1f} ms "
             f"({sba.krylov_its_total} its)")
+        # the same mixed step with the two-level aggregation preconditioner (CG)
+        a_step = prob.opts(precision=fem.PREC_MIXED, krylov=fem.CG, n_load_steps=1, newton_fixed_its=1,
+                           krylov_rtol=args.krylov_rtol, precond=fem.PRECOND_AMG)
+        a_adj = prob.opts(precision=fem.PREC_MIXED, krylov=fem.CG, krylov_rtol=args.krylov_rtol,
+                          adjoint_rtol=args.adjoint_rtol, precond=fem.PRECOND_AMG)
+        t0 = time.perf_counter()
+        n_agg, n_cb = prob.amg_sizes()
+        t_setup = time.perf_counter() - t0
+        for _ in range(2):
+            _, sm = prob.newton_solve(u0=u4, opts=a_step)
+            g_m, _, sma = prob.adjoint_vjp(u5, dJdu, opts=a_adj, want_lambda=False)
+        out["two_level_step"] = {
+            "newton_step_ms": sm.ms_total, "adjoint_grad_ms": sma.ms_total, "value_ms": sm.ms_total + sma.ms_total,
+            "krylov_its": {"newton": sm.krylov_its_total, "adjoint": sma.krylov_its_total},
+            "refresh_ms_per_tangent": sm.ms_assemble,
+            "grad_rel_err_vs_fp64_ref": float(torch.linalg.norm(g_m - g_ref) / torch.linalg.norm(g_ref)),
+            "aggregates": n_agg, "coarse_blocks": n_cb, "setup_s": t_setup,
+            "speedup_over_jacobi": (t_newton + t_adj) / (sm.ms_total + sma.ms_total)}
+        log(f"two-level step: newton {sm.ms_total:.1f} ms ({sm.krylov_its_total} its), adjoint {sma.ms_total:.1f} ms "
+            f"({sma.krylov_its_total} its); {out['two_level_step']['speedup_over_jacobi']:.2f}x the Jacobi step")
         u_ref, _ = prob.newton_solve(opts=prob.opts(precision=fem.PREC_FP64, krylov=fem.CG, krylov_rtol=1e-8,
                                                     newton_rtol=1e-11))
         res = {}
-        forms = (("mixed-" + args.krylov, prec if prec == fem.PREC_MIXED else fem.PREC_MIXED, kry, args.krylov_rtol),
-                 ("fp64-cg", fem.PREC_FP64, fem.CG, args.krylov_rtol),
-                 ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB, args.krylov_rtol))
-        for name, pr, kr, eta in forms:
-            o = prob.opts(precision=pr, krylov=kr, newton_rtol=1e-9, krylov_rtol=eta)
+        forms = (("mixed-" + args.krylov, prec if prec == fem.PREC_MIXED else fem.PREC_MIXED, kry, args.krylov_rtol,
+                  fem.PRECOND_JACOBI),
+                 ("fp64-cg", fem.PREC_FP64, fem.CG, args.krylov_rtol, fem.PRECOND_JACOBI),
+                 ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB, args.krylov_rtol, fem.PRECOND_JACOBI),
+                 ("mixed-cg-two-level", fem.PREC_MIXED, fem.CG, args.krylov_rtol, fem.PRECOND_AMG))
+        for name, pr, kr, eta, pc in forms:
+            o = prob.opts(precision=pr, krylov=kr, newton_rtol=1e-9, krylov_rtol=eta, precond=pc)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             u, st = prob.newton_solve(opts=o)

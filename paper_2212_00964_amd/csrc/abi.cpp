@@ -89,7 +89,7 @@ int fem_default_opts(fem_solve_opts *o) {
         o->adjoint_rtol = 1e-10;
         o->adjoint_max_refine = 20;
         o->profile_spmv = 0;
-        o->amg_smooth_degree = 2;
+        o->amg_smooth_degree = 1;
         o->amg_coarse_degree = 16;
         o->newton_fixed_its = 0;
         o->precond = FEM_PRECOND_JACOBI;

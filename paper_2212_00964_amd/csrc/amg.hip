@@ -16,7 +16,7 @@
 //     deterministic), with a unit diagonal for dropped columns;
 //   * Chebyshev iteration (Saad, Iterative Methods for Sparse Linear Systems, Alg.
 //     12.1) on the interval [lmax / 30, lmax] of the Jacobi-scaled operator, lmax =
-//     min(1.2 x a 20-step power estimate from x_i = sin(1 + i), the Gershgorin bound);
+//     min(1.2 x a 12-step power estimate from x_i = sin(1 + i), the Gershgorin bound);
 //   * one application z = M r: Chebyshev smoothing from 0, restriction of the residual,
 //     Chebyshev steps on A_c from 0, prolongation, Chebyshev smoothing continued from
 //     z.  Equal pre- and post-smoothers make M symmetric, so plain CG applies.
@@ -36,7 +36,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWavesPerBlock = kThreads / 64;
 constexpr int kRedGrid = 1024;
-constexpr int kPowerSteps = 20;
+constexpr int kPowerSteps = 12;
 constexpr double kLmaxSafety = 1.2;
 constexpr double kChebRatio = 30.0;
 constexpr double kDropTol = 1e-10;
@@ -56,8 +56,16 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Sum over the 32-lane half of a wavefront holding this lane; every lane receives it.
+template <typename T>
+__device__ __forceinline__ T half_sum(T v) {
+    v = lane_sum16(v);
+    v += swap_rows(v, v, (threadIdx.x & 31) >= 16);
+    return v;
+}
+
 // ------------------------------------------------------------------ coarse operator
-// One wavefront per coarse block c = (I, J): sum over its fine blocks (i, j) of
+// One 32-lane group per coarse block c = (I, J): sum over its fine blocks (i, j) of
 // P_i^T A_ij P_j.
 template <int ND, int NC, typename T>
 __global__ __launch_bounds__(kThreads) void k_amg_coarse(int64_t nbc, const int64_t *__restrict__ cbp,
@@ -71,15 +79,18 @@ __global__ __launch_bounds__(kThreads) void k_amg_coarse(int64_t nbc, const int6
                                                          const int64_t *__restrict__ row_ptr,
                                                          const T *__restrict__ values, const T *__restrict__ P,
                                                          T *__restrict__ cvals) {
-    const int64_t c = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (c >= nbc) return;  // wave-uniform
+    // one 32-lane group per coarse block (two per wavefront); a group past the end
+    // recomputes the last block and stores nothing, so every lane stays active
+    const int64_t c_raw = int64_t(blockIdx.x) * (kThreads / 32) + (threadIdx.x >> 5);
+    const bool valid = c_raw < nbc;
+    const int64_t c = valid ? c_raw : nbc - 1;
+    const int lane = threadIdx.x & 31;
     T acc[NC][NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k)
 #pragma unroll
         for (int l = 0; l < NC; ++l) acc[k][l] = T(0);
-    for (int64_t q = cbp[c] + lane; q < cbp[c + 1]; q += 64) {
+    for (int64_t q = cbp[c] + lane; q < cbp[c + 1]; q += 32) {
         const int64_t kb = cbk[q];
         const int64_t i = blk_row[kb], j = node_nb[kb];
         const int64_t pos = kb - node_ptr[i];
@@ -114,9 +125,9 @@ __global__ __launch_bounds__(kThreads) void k_amg_coarse(int64_t nbc, const int6
     for (int k = 0; k < NC; ++k)
 #pragma unroll
         for (int l = 0; l < NC; ++l) {
-            T v = wave_sum(acc[k][l]);
+            T v = half_sum(acc[k][l]);
             if (k == l && ((dmask >> k) & 1u)) v = T(1);
-            if (lane == 0) cvals[(c * NC + k) * NC + l] = v;
+            if (valid && lane == 0) cvals[(c * NC + k) * NC + l] = v;
         }
 }
 
@@ -236,25 +247,37 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(int64_t n, const T *__re
 }
 
 // ------------------------------------------------------------------ spectrum bounds
-// Block partials of max_i dinv_i sum_j |A_ij| (Gershgorin), fine CSR rows.
+// Block partials of max_i dinv_i sum_j |A_ij| (Gershgorin) over the fine rows: one
+// 32-lane group per node (lane = neighbour block, the node's ND rows at once).
 template <int ND, typename T>
-__global__ __launch_bounds__(kThreads) void k_gersh_fine(int64_t N, const int64_t *__restrict__ row_ptr,
+__global__ __launch_bounds__(kThreads) void k_gersh_fine(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                          const T *__restrict__ values, const T *__restrict__ dinv,
                                                          double *partials) {
-    __shared__ double red[kWavesPerBlock];
+    __shared__ double red[kThreads / 32];
+    const int lane = threadIdx.x & 31;
+    const int64_t g0 = int64_t(blockIdx.x) * (kThreads / 32) + (threadIdx.x >> 5);
+    const int64_t stride = int64_t(gridDim.x) * (kThreads / 32);
     double m = 0.0;
-    for (int64_t d = int64_t(blockIdx.x) * kThreads + threadIdx.x; d < N; d += int64_t(gridDim.x) * kThreads) {
-        double s = 0.0;
-        for (int64_t q = row_ptr[d]; q < row_ptr[d + 1]; ++q) s += fabs(double(values[q]));
-        m = fmax(m, s * fabs(double(dinv[d])));
-    }
+    for (int64_t n = g0; n < Nn; n += stride) {  // group-uniform loop
+        const int64_t b0 = node_ptr[n];
+        const int deg = int(node_ptr[n + 1] - b0);
+        double sr[ND];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        for (int i = 0; i < ND; ++i) sr[i] = 0.0;
+        for (int l = lane; l < deg; l += 32)
+#pragma unroll
+            for (int i = 0; i < ND; ++i)
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    sr[i] += fabs(double(values[int64_t(ND) * ND * b0 + int64_t(i) * ND * deg + ND * l + k]));
+#pragma unroll
+        for (int i = 0; i < ND; ++i) m = fmax(m, half_sum(sr[i]) * fabs(double(dinv[ND * n + i])));
+    }
+    if (lane == 0) red[threadIdx.x >> 5] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int k = 0; k < kWavesPerBlock; ++k) t = fmax(t, red[k]);
+        for (int k = 0; k < kThreads / 32; ++k) t = fmax(t, red[k]);
         partials[blockIdx.x] = t;
     }
 }
@@ -530,21 +553,31 @@ void chebyshev_run(int64_t n, const Cheb &c, Op op, const T *r, const T *dinv, T
     FEM_HIP(hipGetLastError());
 }
 
-// Largest-eigenvalue bound of dinv A: min(1.2 x power estimate, Gershgorin).
+// Largest-eigenvalue bound of dinv A: min(1.2 x power estimate, Gershgorin bound g).
+// The iterates are scaled by 1/g instead of being normalised (|y_k| stays between
+// (1/30)^k and 1 of the start), so only the last two norms are read back:
+// ||dinv A x_{K-1}|| / ||x_{K-1}|| = g ||y_K|| / ||y_{K-1}||.
 template <typename T, typename Op>
 double lmax_bound(fem_handle *h, int64_t n, Op op, const T *dinv, T *x, T *y, double gersh, hipStream_t s) {
     Amg &a = *h->amg;
+    if (!(gersh > 0.0) || !std::isfinite(gersh)) throw Error(FEM_ENAN, "preconditioner spectrum bound failed");
     hipLaunchKernelGGL((k_power_start<T>), dim3(kRedGrid), dim3(kThreads), 0, s, n, x, a.red);
-    double nrm = std::sqrt(host_sum(a.red, kRedGrid, a.host_red, s));
-    double lam = 0.0;
     for (int k = 0; k < kPowerSteps; ++k) {
-        op(x, y, T(1.0 / nrm));  // y = A x / ||x||
-        hipLaunchKernelGGL((k_power_scale<T>), dim3(kRedGrid), dim3(kThreads), 0, s, n, y, dinv, a.red);
-        lam = std::sqrt(host_sum(a.red, kRedGrid, a.host_red, s));
-        if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(FEM_ENAN, "preconditioner spectrum estimate failed");
-        nrm = lam;
+        op(x, y, T(1.0 / gersh));
+        hipLaunchKernelGGL((k_power_scale<T>), dim3(kRedGrid), dim3(kThreads), 0, s, n, y, dinv,
+                           a.red + (k & 1) * kRedGrid);
         std::swap(x, y);
     }
+    FEM_HIP(hipMemcpyAsync(a.host_red, a.red, 2 * kRedGrid * sizeof(double), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    double n_last = 0.0, n_prev = 0.0;
+    const int last = (kPowerSteps - 1) & 1;
+    for (int b = 0; b < kRedGrid; ++b) {
+        n_last += a.host_red[last * kRedGrid + b];
+        n_prev += a.host_red[(1 - last) * kRedGrid + b];
+    }
+    const double lam = gersh * std::sqrt(n_last / n_prev);
+    if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(FEM_ENAN, "preconditioner spectrum estimate failed");
     return std::min(kLmaxSafety * lam, gersh);
 }
 
@@ -719,8 +752,8 @@ void amg_setup(fem_handle *h) {
     a->cdinv = dev_alloc(h, size_t(na) * nc * sizeof(double));
     a->fine_tmp = dev_alloc(h, 3 * size_t(N) * sizeof(double));
     a->coarse_tmp = dev_alloc(h, 5 * size_t(na) * nc * sizeof(double));
-    a->red = static_cast<double *>(dev_alloc(h, kRedGrid * sizeof(double)));
-    FEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&a->host_red), kRedGrid * sizeof(double)));
+    a->red = static_cast<double *>(dev_alloc(h, 2 * kRedGrid * sizeof(double)));
+    FEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&a->host_red), 2 * kRedGrid * sizeof(double)));
     h->amg = a;
 }
 
@@ -739,7 +772,7 @@ void amg_refresh(fem_handle *h, const T *values, const T *dinv, int precision, i
     Amg &a = *h->amg;
     const Graph &g = h->g;
     AmgView<T> v = view<T>(h);
-    const unsigned Gc = grid_for(a.nbc, kWavesPerBlock);
+    const unsigned Gc = grid_for(a.nbc, kThreads / 32);
 #define FEM_COARSE(ND, NC)                                                                                       \
     hipLaunchKernelGGL((k_amg_coarse<ND, NC, T>), dim3(Gc), dim3(kThreads), 0, s, a.nbc, a.cbp, a.cbk, a.crow,   \
                        a.ccol, a.dropped, g.blk_row, g.node_ptr, g.node_nb, g.row_ptr, values, v.P, v.cvals)
@@ -758,10 +791,10 @@ void amg_refresh(fem_handle *h, const T *values, const T *dinv, int precision, i
                            v.cvals, v.cdinv);
     // spectrum bounds
     if (g.nd == 3)
-        hipLaunchKernelGGL((k_gersh_fine<3, T>), dim3(kRedGrid), dim3(kThreads), 0, s, g.N, g.row_ptr, values, dinv,
+        hipLaunchKernelGGL((k_gersh_fine<3, T>), dim3(kRedGrid), dim3(kThreads), 0, s, g.Nn, g.node_ptr, values, dinv,
                            a.red);
     else
-        hipLaunchKernelGGL((k_gersh_fine<1, T>), dim3(kRedGrid), dim3(kThreads), 0, s, g.N, g.row_ptr, values, dinv,
+        hipLaunchKernelGGL((k_gersh_fine<1, T>), dim3(kRedGrid), dim3(kThreads), 0, s, g.Nn, g.node_ptr, values, dinv,
                            a.red);
     const double gf = host_max(a.red, kRedGrid, a.host_red, s);
     if (a.nc == 6)
