@@ -120,12 +120,13 @@ def cpu_baseline(gpu_counts, size_z=20, method="cg"):
             "newton_ms": newton_ms, "adjoint_ms": adjoint_ms}
 
 
-def j2_path(fem, inputs, n: int, nz: int) -> dict:
+def j2_path(fem, inputs, n: int, nz: int, precond: int = 0) -> dict:
     import torch
     pj = inputs.j2_cylinder(n, nz, n_load_steps=1)
     jp = fem.Problem(pj, "cuda:0")
     jo = jp.opts(precision=fem.PREC_FP64, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-6,
-                 newton_max_it=50, krylov_max_it=100000)
+                 newton_max_it=50, krylov_max_it=100000, precond=precond)
+    pname = "two-level" if precond == fem.PRECOND_AMG else "Jacobi"
     gfull = torch.as_tensor(pj.dirichlet_values, dtype=torch.float64, device="cuda:0")
     uj = torch.zeros(pj.n_dofs, dtype=torch.float64, device="cuda:0")
     n_half = 10
@@ -143,10 +144,10 @@ def j2_path(fem, inputs, n: int, nz: int) -> dict:
         dt = time.perf_counter() - t0
     finally:
         jp.close()
-    log(f"J2 path: {dt:.2f}s ({1e3 * dt / len(lam_path):.0f} ms/load step), sigma_zz peak {max(szz):.1f} "
+    log(f"J2 path ({pname}): {dt:.2f}s ({1e3 * dt / len(lam_path):.0f} ms/load step), sigma_zz peak {max(szz):.1f} "
         f"end {szz[-1]:.1f}, newton its {sum(newton_j)}, krylov its {sum(kry_j)}")
     return {"workload": f"J2 perfect plasticity, cylinder R 5 H 10 as {n}x{n}x{nz} HEX8 ({pj.n_elems} elements, "
-                        f"{pj.n_dofs} dofs), top displacement 0 -> 0.1 -> 0 in 20 load steps, FP64 Jacobi-CG "
+                        f"{pj.n_dofs} dofs), top displacement 0 -> 0.1 -> 0 in 20 load steps, FP64 {pname}-CG "
                         f"(inner rtol 1e-6), Newton rtol 1e-9",
             "s_total": dt, "ms_per_load_step": 1e3 * dt / len(lam_path),
             "top_displacement": [0.1 * x for x in lam_path], "avg_sigma_zz": szz, "newton_its": newton_j,
@@ -357,22 +358,25 @@ def main():
         # elements): solve + compliance + adjoint VJP + sensitivity filter + MMA step
         from paper_2212_00964_amd.topopt import SimpCompliance
         ps = inputs.simp_cantilever(120, 60, 30)
-        sp = fem.Problem(ps, "cuda:0")
-        so = sp.opts(precision=fem.PREC_MIXED, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-3)
-        opt = SimpCompliance(sp, rmin=1.5 * (2.0 / 120), vfrac=0.5, solve_opts=so)
-        opt.step()  # warm-up iteration (its compliance is kept in the history)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n_opt = 4
-        opt.run(n_opt)
-        torch.cuda.synchronize()
-        ms_it = 1e3 * (time.perf_counter() - t0) / n_opt
-        out["simp_loop"] = {"workload": "SIMP cantilever 120x60x30 HEX8 on 2x1x0.5 (216000 elements, 686433 dofs), "
-                                        "theta0 ~ U(0.4, 0.6), rmin 1.5 h, material fraction 0.5, mixed-precision CG",
-                            "ms_per_iteration": ms_it, "compliance": opt.compliance, "material_fraction": opt.volume,
-                            "krylov_its": [s_.krylov_its_total for s_ in opt.stats]}
-        log(f"SIMP loop: {ms_it:.1f} ms/iteration, compliance {[round(c, 4) for c in opt.compliance]}")
-        sp.close()
+        for key, pcs in (("simp_loop", fem.PRECOND_JACOBI), ("simp_loop_two_level", fem.PRECOND_AMG)):
+            sp = fem.Problem(ps, "cuda:0")
+            so = sp.opts(precision=fem.PREC_MIXED, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-3,
+                         precond=pcs)
+            opt = SimpCompliance(sp, rmin=1.5 * (2.0 / 120), vfrac=0.5, solve_opts=so)
+            opt.step()  # warm-up iteration (its compliance is kept in the history)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n_opt = 4
+            opt.run(n_opt)
+            torch.cuda.synchronize()
+            ms_it = 1e3 * (time.perf_counter() - t0) / n_opt
+            pname = "Jacobi" if pcs == fem.PRECOND_JACOBI else "two-level"
+            out[key] = {"workload": "SIMP cantilever 120x60x30 HEX8 on 2x1x0.5 (216000 elements, 686433 dofs), "
+                                    f"theta0 ~ U(0.4, 0.6), rmin 1.5 h, material fraction 0.5, mixed-precision {pname} CG",
+                        "ms_per_iteration": ms_it, "compliance": opt.compliance, "material_fraction": opt.volume,
+                        "krylov_its": [s_.krylov_its_total for s_ in opt.stats]}
+            log(f"SIMP loop ({pname}): {ms_it:.1f} ms/iteration, compliance {[round(c, 4) for c in opt.compliance]}")
+            sp.close()
         # full-field inference: L-BFGS over the nodal source of a Poisson problem on the
         # 1 x 1 x 0.2 box, 50x50x10 HEX8, 250 observed nodes (observations synthesised by
         # the forward solve at the true bimodal source)
@@ -403,11 +407,12 @@ def main():
         # that the averaged stress is recorded after each.  FP64 path: past the limit load
         # the consistent tangent's smallest stiffness falls below FP32 rounding of its
         # deviatoric projection and FP32 CG meets an indefinite matrix.
-        try:
-            out["plasticity_path"] = j2_path(fem, inputs, 48, 96)
-        except fem.FemError as e:
-            out["plasticity_path"] = {"error": str(e)}
-            log(f"J2 path failed: {e}")
+        for key, pcj in (("plasticity_path", fem.PRECOND_JACOBI), ("plasticity_path_two_level", fem.PRECOND_AMG)):
+            try:
+                out[key] = j2_path(fem, inputs, 48, 96, pcj)
+            except fem.FemError as e:
+                out[key] = {"error": str(e)}
+                log(f"J2 path failed: {e}")
         mixed_name = forms[0][0]
         res["speedup_mixed_over_fp64_cg"] = res["fp64-cg"]["s"] / res[mixed_name]["s"]
         res["speedup_mixed_over_fp64_bicgstab"] = res["fp64-bicgstab"]["s"] / res[mixed_name]["s"]
