@@ -753,7 +753,7 @@ constexpr int kGatherSlots = 8;  // slots preloaded per pass
 
 template <int ND, int LAYOUT, typename T>
 __global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *__restrict__ node_ptr,
-                                                     const int32_t *__restrict__ node_nb,
+                                                     const uint8_t *__restrict__ nb_bits,
                                                      const int64_t *__restrict__ ne_ptr,
                                                      const uint8_t *__restrict__ tgt,
                                                      const int64_t *__restrict__ row_ptr,
@@ -783,15 +783,7 @@ __global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *
         if (mask)
 #pragma unroll
             for (int c = 0; c < ND; ++c) rowbits |= int(mask[ND * n + c] != 0) << c;
-        if (lane < deg) {
-            int bits = 0;
-            if (mask) {
-                const int64_t m = node_nb[nb0 + lane];
-#pragma unroll
-                for (int c = 0; c < ND; ++c) bits |= int(mask[ND * m + c] != 0) << c;
-            }
-            nbm[wave][lane] = uint8_t(bits);
-        }
+        if (lane < deg) nbm[wave][lane] = nb_bits[nb0 + lane];
         for (int l = lane; l < deg * BS; l += W) a[l] = T(0);
         const int64_t k1 = ne_ptr[n + 1];
         for (int64_t k0 = ne_ptr[n]; k0 < k1; k0 += kGatherSlots) {
@@ -1020,11 +1012,11 @@ void launch_tangent(const fem_handle *h, const double *u, const double *theta, T
         if (node_gather) {
             if (layout == LAYOUT_SYM)
                 hipLaunchKernelGGL((k_gather_node<ND, LAYOUT_SYM, T>), dim3(gather_grid(h)), dim3(256), 0, s,
-                                   g.Nn, g.node_ptr, g.node_nb, g.ne_ptr, g.tgt, g.row_ptr, g.bdiag, g.up_base,
+                                   g.Nn, g.node_ptr, g.nb_bits, g.ne_ptr, g.tgt, g.row_ptr, g.bdiag, g.up_base,
                                    h->m.mask, ke, values, dinv, bj, h->status);
             else
                 hipLaunchKernelGGL((k_gather_node<ND, LAYOUT_CSR, T>), dim3(gather_grid(h)), dim3(256), 0, s,
-                                   g.Nn, g.node_ptr, g.node_nb, g.ne_ptr, g.tgt, g.row_ptr, g.bdiag, g.up_base,
+                                   g.Nn, g.node_ptr, g.nb_bits, g.ne_ptr, g.tgt, g.row_ptr, g.bdiag, g.up_base,
                                    h->m.mask, ke, values, dinv, bj, h->status);
         } else {
             if (layout == LAYOUT_SYM)

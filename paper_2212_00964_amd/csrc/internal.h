@@ -62,6 +62,7 @@ struct Graph {
     int64_t *node_ptr = nullptr;  // [Nn+1] first block of node n
     int32_t *node_nb = nullptr;   // [nnzb] neighbour node of each block, ascending per node
     int16_t *node_dnb = nullptr;  // [nnzb] node_nb - row node, when every offset fits 16 bits (else null)
+    uint8_t *nb_bits = nullptr;   // [nnzb] Dirichlet bits of the neighbour's dofs (bit c: dof c)
     int32_t *blk_row = nullptr;   // [nnzb] owning node of each block
     int32_t *mirror = nullptr;    // [nnzb] block (m, n) for block (n, m)
     int32_t *bdiag = nullptr;     // [Nn] block (n, n)

@@ -190,6 +190,14 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
             }
         if (fits) g.node_dnb = upload(h, dnb);
     }
+    {  // Dirichlet bits of every block's column node (one load per neighbour in the gather)
+        std::vector<uint8_t> bits(nnzb, 0);
+        const std::vector<uint8_t> &mk = h->m.host_mask;
+        if (!mk.empty())
+            for (int64_t k = 0; k < nnzb; ++k)
+                for (int c = 0; c < nd; ++c) bits[k] |= uint8_t((mk[int64_t(nd) * node_nb[k] + c] != 0) << c);
+        g.nb_bits = upload(h, bits);
+    }
     g.blk_row = upload(h, blk_row);
     g.mirror = upload(h, mirror);
     g.bdiag = upload(h, bdiag);
