@@ -317,6 +317,41 @@ def cylinder_mesh(n: int, nz: int, R: float = 5.0, H: float = 10.0):
     return out, conn
 
 
+def fan_mesh(k: int = 8, layers: int = 4, R: float = 1.0, H: float = 1.0):
+    """HEX8 prism over the regular k-gon of circumradius R: the polygon is split into k
+    kites (centre, midpoint of edge i, corner i+1, midpoint of edge i+1) and extruded in
+    `layers` layers to height H.  The nodes on the axis are shared by 2k elements and
+    have 3 (2k + 1) neighbours (51 for k = 8): a mesh outside the structured-grid
+    degrees (at most 8 elements and 27 neighbours per node)."""
+    a = 2.0 * np.pi * np.arange(k) / k
+    v = R * np.stack([np.cos(a), np.sin(a)], axis=1)
+    m = 0.5 * (v + np.roll(v, -1, axis=0))  # m[i] halves the edge from corner i to i+1
+    pts = np.vstack([np.zeros((1, 2)), m, v])  # 0: centre, 1..k: midpoints, k+1..2k: corners
+    quads = np.array([[0, 1 + i, k + 1 + (i + 1) % k, 1 + (i + 1) % k] for i in range(k)])
+    npl = 2 * k + 1
+    coords = np.vstack([np.column_stack([pts, np.full(npl, H * l / layers)]) for l in range(layers + 1)])
+    conn = np.vstack([np.hstack([quads + l * npl, quads + (l + 1) * npl]) for l in range(layers)])
+    return coords, conn.astype(np.int32)
+
+
+def nh_fan(k: int = 8, layers: int = 4, stretch: float = 1.1, n_load_steps: int = 2, seed: int = 0,
+           sigma: float = 0.3, mu: float = float(np.log(10.0)), bulk_ratio: float = 10.0) -> Problem:
+    """Compressible neo-Hookean fan prism (fan_mesh) stretched along its axis: the bottom
+    face fixed, the top face moved by (stretch-1) H along z with u_x = u_y = 0;
+    per-element shear modulus lognormal."""
+    H = 1.0
+    coords, conn = fan_mesh(k, layers, 1.0, H)
+    bottom = np.isclose(coords[:, 2], 0.0)
+    top = np.isclose(coords[:, 2], H)
+    mask = _dof_mask(bottom | top, 3, (0, 1, 2))
+    vals = np.zeros((coords.shape[0], 3))
+    vals[top, 2] = (stretch - 1.0) * H
+    return Problem(
+        name=f"nh-fan-{k}x{layers}", coords=coords, conn=conn, ndpn=3, model=NEO_HOOKEAN,
+        theta=lognormal_field(conn.shape[0], mu, sigma, seed), dirichlet_mask=mask, dirichlet_values=vals.ravel(),
+        bulk_ratio=bulk_ratio, n_load_steps=n_load_steps, krylov=CG, lengths=(2.0, 2.0, H))
+
+
 def j2_cylinder(n: int = 8, nz: int = 16, R: float = 5.0, H: float = 10.0, E: float = 70e3, nu: float = 0.3,
                 yield_stress: float = 250.0, disp: float = 0.1, n_load_steps: int = 10) -> Problem:
     """Perfect J2 plasticity in uniaxial tension of a cylinder (radius R, height H): bottom

@@ -110,6 +110,7 @@ SOLVES = {
     "nh-9x7x6-5steps": gen.nh_tensile(9, 7, 6, n_load_steps=5, seed=0, distort_seed=1),
     "cantilever-9x4x5-relabelled": CASES["cantilever-9x4x5-relabelled"],
     "poisson-9-distorted": CASES["poisson-9-distorted"],
+    "nh-fan-8x4": gen.nh_fan(8, 4, n_load_steps=2, seed=6),
 }
 
 

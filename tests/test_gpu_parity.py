@@ -42,6 +42,9 @@ def cases_small():
         "nh-5x3x7-lognormal": gen.nh_tensile(5, 3, 7, n_load_steps=2, seed=4, distort_seed=5),
         "simp-6x3x2": gen.simp_cantilever(6, 3, 2, seed=0),
         "single-element-nh": gen.nh_tensile(1, 1, 1, n_load_steps=2),
+        # axis nodes with 16 elements and 51 neighbours: the general gather and the
+        # SpMV's high-degree pass
+        "nh-fan-8x4": gen.nh_fan(8, 4, n_load_steps=2, seed=6),
     }
 
 
@@ -115,10 +118,11 @@ def test_assembly_fp64_and_fp32(name):
     prob.close()
 
 
+@pytest.mark.parametrize("name", ["nh-5x3x7-lognormal", "nh-fan-8x4"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("transpose", [False, True])
-def test_spmv(dtype, transpose):
-    p = CASES["nh-5x3x7-lognormal"]
+def test_spmv(name, dtype, transpose):
+    p = CASES[name]
     u = _state(p, 1)
     pat = orc.Pattern(p)
     _, K_ref = orc.assemble(p, pat, u)
@@ -192,7 +196,8 @@ def test_wide_numbering_takes_32bit_indices():
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["poisson-5x4x3-distorted", "nh-5x3x7-lognormal", "cantilever-7x3x5-distorted"])
+@pytest.mark.parametrize("name", ["poisson-5x4x3-distorted", "nh-5x3x7-lognormal", "cantilever-7x3x5-distorted",
+                                  "nh-fan-8x4"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_symmetric_block_layout_assembly_and_spmv(name, dtype):
     p = CASES[name]
@@ -215,7 +220,8 @@ def test_symmetric_block_layout_assembly_and_spmv(name, dtype):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["cantilever-7x3x5-distorted", "nh-5x3x7-lognormal", "poisson-5x4x3-distorted"])
+@pytest.mark.parametrize("name", ["cantilever-7x3x5-distorted", "nh-5x3x7-lognormal", "poisson-5x4x3-distorted",
+                                  "nh-fan-8x4"])
 def test_apply_tangent_matches_assembled_operator(name):
     p = CASES[name]
     u = _state(p, 4)
@@ -236,6 +242,7 @@ SOLVE_CASES = {
     "nh-5x3x7": (CASES["nh-5x3x7-lognormal"], "direct"),
     "nh-9x7x6-5steps": (gen.nh_tensile(9, 7, 6, n_load_steps=5, seed=0, distort_seed=1), "direct"),
     "single-element": (CASES["single-element-nh"], "direct"),
+    "nh-fan-8x4": (CASES["nh-fan-8x4"], "direct"),
 }
 
 
@@ -280,7 +287,7 @@ def test_nh_homogeneous_closed_form_on_gpu(precision):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["cantilever-7x3x5", "nh-9x7x6-5steps", "poisson-8cube"])
+@pytest.mark.parametrize("name", ["cantilever-7x3x5", "nh-9x7x6-5steps", "poisson-8cube", "nh-fan-8x4"])
 @pytest.mark.parametrize("krylov", [fem.CG, fem.BICGSTAB])
 @pytest.mark.parametrize("precision", [fem.PREC_FP64, fem.PREC_MIXED])
 def test_newton_block_jacobi_matches_oracle(name, krylov, precision):

@@ -512,3 +512,24 @@ def test_transposed_krylov_adjoint_equals_direct():
     g2, l2 = orc.adjoint_vjp(p, u, dJdu, linear="bicgstab")
     assert np.linalg.norm(l2 - l1) <= 1e-10 * np.linalg.norm(l1)
     assert np.linalg.norm(g2 - g1) <= 1e-10 * np.linalg.norm(g1)
+
+
+def test_fan_mesh_volume_and_high_degree_nodes():
+    """The fan prism used for the general gather and the SpMV's high-degree pass: every
+    element has a positive Jacobian at its Gauss points, the volume is the k-gon's area
+    times the height (straight-sided prisms: 2x2x2 Gauss is exact), and the axis nodes
+    carry 2k elements and 3 (2k + 1) neighbours."""
+    from oracle import topopt
+
+    k, layers = 8, 4
+    p = gen.nh_fan(k, layers)
+    v = topopt.element_volumes(p)  # raises if det J <= 0 at a Gauss point
+    assert np.all(v > 0)
+    assert abs(v.sum() - 0.5 * k * np.sin(2 * np.pi / k)) <= 1e-13
+    axis = np.flatnonzero(np.hypot(p.coords[:, 0], p.coords[:, 1]) < 1e-12)
+    assert axis.size == layers + 1
+    counts = np.bincount(p.conn.ravel(), minlength=p.n_nodes)
+    assert counts[axis[1:-1]].tolist() == [2 * k] * (layers - 1)
+    pat = orc.Pattern(p)
+    deg = np.diff(pat.row_ptr)[::3] // 3
+    assert deg.max() == 3 * (2 * k + 1) and deg[axis[1]] == 3 * (2 * k + 1)
