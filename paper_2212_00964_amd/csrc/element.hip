@@ -514,7 +514,7 @@ __global__ __launch_bounds__(256) void k_gather_vec(int64_t N, const int64_t *__
 // scratch[((kpos[e*8 + a])*8 + b)*ND*ND + i*ND + k]: the row blocks feeding node
 // conn[e][a] are contiguous, so the gather reads each node's 8 row blocks as one run.
 template <int MODEL, int ND, typename T>
-__global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const double *__restrict__ coords,
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 3 : 2) void k_element_tangent(int64_t Ne, const double *__restrict__ coords,
                                                               const int32_t *__restrict__ conn,
                                                               const int32_t *__restrict__ kpos, Material mat,
                                                               const double *__restrict__ theta,
@@ -562,6 +562,15 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
             }
             __syncthreads();
             T cw = dJ * s.c, c23 = T(2.0 / 3.0) * cw, aw = dJ * s.alpha, bw = dJ * s.beta;
+            // block (a, b): aw h_i hb_k + bw hb_i h_k - c23 (f_i hb_k + h_i fb_k) + delta_ik cw g.gb,
+            // grouped by the factors of this node so each entry takes three FMAs
+            T P[3], Q[3], R[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                P[i] = aw * h[i] - c23 * f[i];
+                Q[i] = bw * h[i];
+                R[i] = -c23 * h[i];
+            }
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const T *o = el + b * NV;
@@ -571,9 +580,11 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        T v = aw * h[i] * hb[k] + bw * hb[i] * h[k] - c23 * (f[i] * hb[k] + h[i] * fb[k]);
+                        T v = fma(P[i], hb[k], K[b][i][k]);
+                        v = fma(hb[i], Q[k], v);
+                        v = fma(R[i], fb[k], v);
                         if (i == k) v += sdot;
-                        K[b][i][k] += v;
+                        K[b][i][k] = v;
                     }
             }
             __syncthreads();
@@ -591,6 +602,15 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
             }
             __syncthreads();
             T lw = dJ * s.lw, mw = dJ * s.mup, bw = dJ * s.beta;
+            // block (a, b): lw g_i gb_k + mw g_k gb_i - bw sg_i sb_k + delta_ik mw g.gb, three FMAs
+            // per entry with this node's factors taken first
+            T P[3], Q[3], R[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                P[i] = lw * g[i];
+                Q[i] = mw * g[i];
+                R[i] = -bw * sg[i];
+            }
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const T *o = el + b * NV;
@@ -600,9 +620,11 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        T v = lw * g[i] * gb[k] + mw * g[k] * gb[i] - bw * sg[i] * sb[k];
+                        T v = fma(P[i], gb[k], K[b][i][k]);
+                        v = fma(gb[i], Q[k], v);
+                        v = fma(R[i], sb[k], v);
                         if (i == k) v += sdot;
-                        K[b][i][k] += v;
+                        K[b][i][k] = v;
                     }
             }
             __syncthreads();
@@ -613,6 +635,12 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
             if constexpr (MODEL == FEM_LINEAR_ELASTIC) {
                 T nu = T(mat.nu);
                 T lw = dJ * mod * nu / ((T(1) + nu) * (T(1) - T(2) * nu)), mw = dJ * mod / (T(2) * (T(1) + nu));
+                T P[3], Q[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    P[i] = lw * g[i];
+                    Q[i] = mw * g[i];
+                }
 #pragma unroll
                 for (int b = 0; b < 8; ++b) {
                     const T *o = el + b * NV;
@@ -622,9 +650,11 @@ __global__ __launch_bounds__(kThreads) void k_element_tangent(int64_t Ne, const 
                     for (int i = 0; i < 3; ++i)
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
-                            T v = lw * g[i] * gb[k] + mw * g[k] * gb[i];
+                            // lw g_i gb_k + mw g_k gb_i + delta_ik mw g.gb
+                            T v = fma(P[i], gb[k], K[b][i][k]);
+                            v = fma(gb[i], Q[k], v);
                             if (i == k) v += sdot;
-                            K[b][i][k] += v;
+                            K[b][i][k] = v;
                         }
                 }
             } else {
