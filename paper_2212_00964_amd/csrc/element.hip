@@ -197,12 +197,15 @@ __device__ __forceinline__ void symvec(const T S[6], const T x[3], T y[3]) {
 // Flux applied to this lane's shape gradient: out = f(G) g (the integrand of R_e
 // at one Gauss point, before the quadrature weight).  Returns false if det F <= 0.
 // hq: the Gauss point's committed J2 state (unused by the other laws).
+// First Piola flux P(G) as a 3x3 matrix (rows >= ND are zero): the element residual
+// of node a is sum_q detJ P g_a.
 template <int MODEL, typename T>
-__device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][3], const T g[3], T out[3],
-                                         const double *hq) {
+__device__ __forceinline__ bool flux_mat(const Material &m, T mod, const T G[3][3], T P[3][3], const double *hq) {
     if constexpr (MODEL == FEM_POISSON) {
-        out[0] = mod * (G[0][0] * g[0] + G[0][1] * g[1] + G[0][2] * g[2]);
-        out[1] = out[2] = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[i][j] = (i == 0) ? mod * G[0][j] : T(0);
         return true;
     } else if constexpr (MODEL == FEM_LINEAR_ELASTIC) {
         T nu = T(m.nu);
@@ -210,32 +213,35 @@ __device__ __forceinline__ bool flux_dot(const Material &m, T mod, const T G[3][
         T tr = G[0][0] + G[1][1] + G[2][2];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            out[i] = lam * tr * g[i] + mu * ((G[i][0] + G[0][i]) * g[0] + (G[i][1] + G[1][i]) * g[1] +
-                                             (G[i][2] + G[2][i]) * g[2]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[i][j] = mu * (G[i][j] + G[j][i]) + (i == j ? lam * tr : T(0));
         return true;
     } else if constexpr (MODEL == FEM_J2_PLASTIC) {
         J2State<T> s;
         j2_state(m, mod, G, hq, s);
-        symvec(s.sig, g, out);
+        const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[i][j] = s.sig[idx[i][j]];
         return true;
     } else {
         NHState<T> s;
         bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
-        T f[3], h[3];
-        matvec3(s.F, g, f);
-        matvec3(s.H, g, h);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) out[i] = s.c * f[i] + s.pcoef * h[i];
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[i][j] = s.c * s.F[i][j] + s.pcoef * s.H[i][j];
         return ok;
     }
 }
 
-// Directional derivative of the flux: out = (A : dG) g with A the tangent at G.
+// Directional derivative of the flux, dP = A(G) : dG, as a 3x3 matrix.
 template <int MODEL, typename T>
-__device__ __forceinline__ bool dflux_dot(const Material &m, T mod, const T G[3][3], const T dG[3][3], const T g[3],
-                                          T out[3], const double *hq) {
+__device__ __forceinline__ bool dflux_mat(const Material &m, T mod, const T G[3][3], const T dG[3][3], T dP[3][3],
+                                          const double *hq) {
     if constexpr (MODEL == FEM_POISSON || MODEL == FEM_LINEAR_ELASTIC) {
-        return flux_dot<MODEL, T>(m, mod, dG, g, out, hq);  // linear laws
+        return flux_mat<MODEL, T>(m, mod, dG, dP, hq);  // linear laws
     } else if constexpr (MODEL == FEM_J2_PLASTIC) {
         J2State<T> s;
         j2_state(m, mod, G, hq, s);
@@ -243,14 +249,12 @@ __device__ __forceinline__ bool dflux_dot(const Material &m, T mod, const T G[3]
         const T sd = s.dev[0] * dG[0][0] + s.dev[1] * dG[1][1] + s.dev[2] * dG[2][2] +
                      s.dev[3] * (dG[1][2] + dG[2][1]) + s.dev[4] * (dG[0][2] + dG[2][0]) +
                      s.dev[5] * (dG[0][1] + dG[1][0]);
-        T sg[3];
-        symvec(s.dev, g, sg);
+        const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            out[i] = s.lw * tr * g[i] +
-                     s.mup * ((dG[i][0] + dG[0][i]) * g[0] + (dG[i][1] + dG[1][i]) * g[1] +
-                              (dG[i][2] + dG[2][i]) * g[2]) -
-                     s.beta * sd * sg[i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                dP[i][j] = s.mup * (dG[i][j] + dG[j][i]) - s.beta * sd * s.dev[idx[i][j]] + (i == j ? s.lw * tr : T(0));
         return true;
     } else {
         NHState<T> s;
@@ -263,19 +267,39 @@ __device__ __forceinline__ bool dflux_dot(const Material &m, T mod, const T G[3]
                 HdF += s.H[i][j] * dG[i][j];
                 FdF += s.F[i][j] * dG[i][j];
             }
-        T f[3], h[3], dFg[3], mv[3], Hm[3];
-        matvec3(s.F, g, f);
-        matvec3(s.H, g, h);
-        matvec3(dG, g, dFg);
+        // dF^T H, then H (dF^T H)
+        T DH[3][3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) mv[k] = dG[0][k] * h[0] + dG[1][k] * h[1] + dG[2][k] * h[2];  // dF^T h
-        matvec3(s.H, mv, Hm);
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) DH[k][j] = dG[0][k] * s.H[0][j] + dG[1][k] * s.H[1][j] + dG[2][k] * s.H[2][j];
         T c23 = T(2.0 / 3.0) * s.c;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            out[i] = s.c * dFg[i] - c23 * (f[i] * HdF + h[i] * FdF) + s.alpha * h[i] * HdF + s.beta * Hm[i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const T HDH = s.H[i][0] * DH[0][j] + s.H[i][1] * DH[1][j] + s.H[i][2] * DH[2][j];
+                dP[i][j] = s.c * dG[i][j] - c23 * (s.F[i][j] * HdF + s.H[i][j] * FdF) + s.alpha * s.H[i][j] * HdF +
+                           s.beta * HDH;
+            }
         return ok;
     }
+}
+
+// Reference gradients dN_b(xi_q) of the 8 shape functions at Gauss point q.
+template <typename T>
+__device__ __forceinline__ void ref_grad(int b, int q, T dN[3]) {
+    const T gq = T(0.57735026918962576451);  // 1/sqrt(3)
+    T l[3], sg[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const T xi = ((q >> j) & 1) ? gq : -gq;
+        sg[j] = T(ref_sign(b, j));
+        l[j] = T(0.5) * (T(1) + sg[j] * xi);
+    }
+    dN[0] = T(0.5) * sg[0] * l[1] * l[2];
+    dN[1] = T(0.5) * sg[1] * l[0] * l[2];
+    dN[2] = T(0.5) * sg[2] * l[0] * l[1];
 }
 
 struct ElemIds {
@@ -322,6 +346,13 @@ enum { VEC_RESIDUAL = 0, VEC_JVP = 1, VEC_VJP = 2, VEC_LIFT = 3, VEC_MASS = 4 };
 // VEC_JVP:      scratch[s][i] = sum_q detJ (A(grad u) : grad v) g_a  (v with Dirichlet dofs zeroed)
 // VEC_VJP:      g[e] = -m'(theta_e) sum_{a,i free} lam_a,i sum_q detJ f_unit(grad u) g_a
 // VEC_LIFT:     as VEC_JVP but with v used on every dof (v is nonzero on Dirichlet dofs only)
+//
+// Two phases, 8 lanes per element.  Lane q evaluates Gauss point q: the Jacobian J_q
+// from the element's node coordinates, the field gradients G = G_ref J_q^{-1}, the
+// flux P (or its derivative) and M_q = detJ_q P J_q^{-T}, which it leaves in LDS.
+// Lane a then sums its node's terms, sum_q M_q dN_a(xi_q) (= sum_q detJ P g_a).  The
+// per-point work (Jacobian inverse, constitutive update) is done once per point
+// instead of once per lane.
 template <int MODEL, int ND, int MODE>
 __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const double *__restrict__ coords,
                                                           const int32_t *__restrict__ conn,
@@ -332,34 +363,80 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ hist, double *__restrict__ out,
                                                           int *status) {
+    constexpr bool kDir = MODE == VEC_JVP || MODE == VEC_LIFT;
+    constexpr int NF = 3 + ND + (MODE == VEC_RESIDUAL ? 0 : ND);  // node values staged per lane
+    __shared__ double nodes[kElemsPerBlock][8][NF];
+    __shared__ double Ms[kElemsPerBlock][8][9];
     ElemIds id = elem_ids(Ne);
     double X[3], U[ND], W[ND];
     load_node<ND, double>(coords, conn, u, nullptr, id, X, U, true);
     if (MODE != VEC_RESIDUAL)
         load_node<ND, double>(coords, conn, v, MODE == VEC_LIFT ? nullptr : mask, id, X, W, MODE != VEC_VJP);
-    double th = theta[id.e];
-    double mod = (MODE == VEC_VJP) ? 1.0 : modulus(mat, th);
-    double acc[3] = {0, 0, 0};
-    bool mesh_ok = true, mat_ok = true;
-#pragma unroll 1
-    for (int q = 0; q < 8; ++q) {
-        double g[3];
-        double dJ = gp_geometry(id.a, q, X, g);
-        mesh_ok &= dJ > 0.0;
-        double G[3][3], o[3];
-        field_grad<ND>(U, g, G);
-        const double *hq = MODEL == FEM_J2_PLASTIC ? hist + (id.e * 8 + q) * 12 : nullptr;
-        if (MODE == VEC_JVP || MODE == VEC_LIFT) {
-            double dG[3][3];
-            field_grad<ND>(W, g, dG);
-            mat_ok &= dflux_dot<MODEL, double>(mat, mod, G, dG, g, o, hq);
-        } else {
-            mat_ok &= flux_dot<MODEL, double>(mat, mod, G, g, o, hq);
-        }
+    double *mine = nodes[id.el][id.a];
 #pragma unroll
-        for (int i = 0; i < ND; ++i) acc[i] += dJ * o[i];
+    for (int i = 0; i < 3; ++i) mine[i] = X[i];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) mine[3 + i] = U[i];
+    if constexpr (MODE != VEC_RESIDUAL)
+#pragma unroll
+        for (int i = 0; i < ND; ++i) mine[3 + ND + i] = W[i];
+    const double th = theta[id.e];
+    const double mod = (MODE == VEC_VJP) ? 1.0 : modulus(mat, th);
+    __syncthreads();
+    // phase 1: this lane's Gauss point q = a
+    bool mesh_ok, mat_ok;
+    {
+        const int q = id.a;
+        double J[3][3] = {}, Gr[3][3] = {}, Wr[3][3] = {};  // Jacobian, reference gradients of u and v
+#pragma unroll 2
+        for (int b = 0; b < 8; ++b) {
+            double dN[3];
+            ref_grad<double>(b, q, dN);
+            const double *nb = nodes[id.el][b];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    J[i][j] = fma(nb[i], dN[j], J[i][j]);
+                    if (i < ND) Gr[i][j] = fma(nb[3 + i], dN[j], Gr[i][j]);
+                    if (kDir && i < ND) Wr[i][j] = fma(nb[3 + ND + i], dN[j], Wr[i][j]);
+                }
+        }
+        const double d = det3(J);
+        mesh_ok = d > 0.0;
+        double Bt[3][3];  // J^{-T}: g_b = Bt dN_b
+        inv_transpose3(J, d, Bt);
+        double G[3][3], dG[3][3], P[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                G[i][j] = Gr[i][0] * Bt[j][0] + Gr[i][1] * Bt[j][1] + Gr[i][2] * Bt[j][2];
+                dG[i][j] = Wr[i][0] * Bt[j][0] + Wr[i][1] * Bt[j][1] + Wr[i][2] * Bt[j][2];
+            }
+        const double *hq = MODEL == FEM_J2_PLASTIC ? hist + (id.e * 8 + q) * 12 : nullptr;
+        if constexpr (kDir) mat_ok = dflux_mat<MODEL, double>(mat, mod, G, dG, P, hq);
+        else mat_ok = flux_mat<MODEL, double>(mat, mod, G, P, hq);
+        double *mq = Ms[id.el][q];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) mq[i * 3 + k] = d * (P[i][0] * Bt[0][k] + P[i][1] * Bt[1][k] + P[i][2] * Bt[2][k]);
     }
-    if (id.valid && id.a == 0 && (!mesh_ok || !mat_ok))
+    __syncthreads();
+    // phase 2: this lane's node a
+    double acc[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) acc[i] = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < 8; ++q) {
+        double dN[3];
+        ref_grad<double>(id.a, q, dN);
+        const double *mq = Ms[id.el][q];
+#pragma unroll
+        for (int i = 0; i < ND; ++i) acc[i] += mq[i * 3] * dN[0] + mq[i * 3 + 1] * dN[1] + mq[i * 3 + 2] * dN[2];
+    }
+    if (id.valid && (!mesh_ok || !mat_ok))
         atomicOr(status, (!mesh_ok ? ST_MESH : 0) | (!mat_ok ? ST_INVERTED : 0));
     if (MODE == VEC_VJP) {
         double s = 0.0;
