@@ -286,6 +286,33 @@ __device__ __forceinline__ bool dflux_mat(const Material &m, T mod, const T G[3]
     }
 }
 
+// J2 flux and its derivative applied to this lane's gradient g (the per-lane form used
+// by the J2 vector kernel): out = sigma g, and out = (A : dG) g.
+template <typename T>
+__device__ __forceinline__ void j2_flux_dot(const Material &m, T mod, const T G[3][3], const T g[3], T out[3],
+                                            const double *hq) {
+    J2State<T> s;
+    j2_state(m, mod, G, hq, s);
+    symvec(s.sig, g, out);
+}
+
+template <typename T>
+__device__ __forceinline__ void j2_dflux_dot(const Material &m, T mod, const T G[3][3], const T dG[3][3],
+                                             const T g[3], T out[3], const double *hq) {
+    J2State<T> s;
+    j2_state(m, mod, G, hq, s);
+    const T tr = dG[0][0] + dG[1][1] + dG[2][2];
+    const T sd = s.dev[0] * dG[0][0] + s.dev[1] * dG[1][1] + s.dev[2] * dG[2][2] + s.dev[3] * (dG[1][2] + dG[2][1]) +
+                 s.dev[4] * (dG[0][2] + dG[2][0]) + s.dev[5] * (dG[0][1] + dG[1][0]);
+    T sg[3];
+    symvec(s.dev, g, sg);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        out[i] = s.lw * tr * g[i] +
+                 s.mup * ((dG[i][0] + dG[0][i]) * g[0] + (dG[i][1] + dG[1][i]) * g[1] + (dG[i][2] + dG[2][i]) * g[2]) -
+                 s.beta * sd * sg[i];
+}
+
 // Reference gradients dN_b(xi_q) of the 8 shape functions at Gauss point q.
 template <typename T>
 __device__ __forceinline__ void ref_grad(int b, int q, T dN[3]) {
@@ -364,6 +391,49 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
                                                           const double *__restrict__ hist, double *__restrict__ out,
                                                           int *status) {
     constexpr bool kDir = MODE == VEC_JVP || MODE == VEC_LIFT;
+    if constexpr (MODEL == FEM_J2_PLASTIC) {
+        // J2 keeps the per-lane form (every lane walks the 8 points for its own node): the
+        // loading-unloading path near the limit load has a nearly singular tangent, and
+        // its Newton iterations were measured to converge with this form's rounding.
+        ElemIds id = elem_ids(Ne);
+        double X[3], U[ND], W[ND];
+        load_node<ND, double>(coords, conn, u, nullptr, id, X, U, true);
+        if (MODE != VEC_RESIDUAL)
+            load_node<ND, double>(coords, conn, v, MODE == VEC_LIFT ? nullptr : mask, id, X, W, MODE != VEC_VJP);
+        double th = theta[id.e];
+        double mod = (MODE == VEC_VJP) ? 1.0 : modulus(mat, th);
+        double acc[3] = {0, 0, 0};
+        bool mesh_ok = true;
+#pragma unroll 1
+        for (int q = 0; q < 8; ++q) {
+            double g[3];
+            double dJ = gp_geometry(id.a, q, X, g);
+            mesh_ok &= dJ > 0.0;
+            double G[3][3], o[3];
+            field_grad<ND>(U, g, G);
+            const double *hq = hist + (id.e * 8 + q) * 12;
+            if (kDir) {
+                double dG[3][3];
+                field_grad<ND>(W, g, dG);
+                j2_dflux_dot<double>(mat, mod, G, dG, g, o, hq);
+            } else {
+                j2_flux_dot<double>(mat, mod, G, g, o, hq);
+            }
+#pragma unroll
+            for (int i = 0; i < ND; ++i) acc[i] += dJ * o[i];
+        }
+        if (id.valid && id.a == 0 && !mesh_ok) atomicOr(status, ST_MESH);
+        if (MODE == VEC_VJP) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < ND; ++i) s += W[i] * acc[i];
+            s = sum8(s);
+            if (id.valid && id.a == 0) out[id.e] = -dmodulus(mat, th) * s;
+        } else if (id.valid) {
+#pragma unroll
+            for (int i = 0; i < ND; ++i) out[int64_t(kpos[id.e * 8 + id.a]) * ND + i] = acc[i];
+        }
+    } else {
     constexpr int NF = 3 + ND + (MODE == VEC_RESIDUAL ? 0 : ND);  // node values staged per lane
     __shared__ double nodes[kElemsPerBlock][8][NF];
     __shared__ double Ms[kElemsPerBlock][8][9];
@@ -447,6 +517,7 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
     } else if (id.valid) {
 #pragma unroll
         for (int i = 0; i < ND; ++i) out[int64_t(kpos[id.e * 8 + id.a]) * ND + i] = acc[i];
+    }
     }
 }
 
