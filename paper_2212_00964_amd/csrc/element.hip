@@ -216,16 +216,8 @@ __device__ __forceinline__ bool flux_mat(const Material &m, T mod, const T G[3][
 #pragma unroll
             for (int j = 0; j < 3; ++j) P[i][j] = mu * (G[i][j] + G[j][i]) + (i == j ? lam * tr : T(0));
         return true;
-    } else if constexpr (MODEL == FEM_J2_PLASTIC) {
-        J2State<T> s;
-        j2_state(m, mod, G, hq, s);
-        const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) P[i][j] = s.sig[idx[i][j]];
-        return true;
     } else {
+        static_assert(MODEL == FEM_NEO_HOOKEAN, "the J2 law uses j2_flux_dot");
         NHState<T> s;
         bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
 #pragma unroll
@@ -242,21 +234,8 @@ __device__ __forceinline__ bool dflux_mat(const Material &m, T mod, const T G[3]
                                           const double *hq) {
     if constexpr (MODEL == FEM_POISSON || MODEL == FEM_LINEAR_ELASTIC) {
         return flux_mat<MODEL, T>(m, mod, dG, dP, hq);  // linear laws
-    } else if constexpr (MODEL == FEM_J2_PLASTIC) {
-        J2State<T> s;
-        j2_state(m, mod, G, hq, s);
-        const T tr = dG[0][0] + dG[1][1] + dG[2][2];
-        const T sd = s.dev[0] * dG[0][0] + s.dev[1] * dG[1][1] + s.dev[2] * dG[2][2] +
-                     s.dev[3] * (dG[1][2] + dG[2][1]) + s.dev[4] * (dG[0][2] + dG[2][0]) +
-                     s.dev[5] * (dG[0][1] + dG[1][0]);
-        const int idx[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                dP[i][j] = s.mup * (dG[i][j] + dG[j][i]) - s.beta * sd * s.dev[idx[i][j]] + (i == j ? s.lw * tr : T(0));
-        return true;
     } else {
+        static_assert(MODEL == FEM_NEO_HOOKEAN, "the J2 law uses j2_dflux_dot");
         NHState<T> s;
         bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
         T HdF = T(0), FdF = T(0);
@@ -484,9 +463,8 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
                 G[i][j] = Gr[i][0] * Bt[j][0] + Gr[i][1] * Bt[j][1] + Gr[i][2] * Bt[j][2];
                 dG[i][j] = Wr[i][0] * Bt[j][0] + Wr[i][1] * Bt[j][1] + Wr[i][2] * Bt[j][2];
             }
-        const double *hq = MODEL == FEM_J2_PLASTIC ? hist + (id.e * 8 + q) * 12 : nullptr;
-        if constexpr (kDir) mat_ok = dflux_mat<MODEL, double>(mat, mod, G, dG, P, hq);
-        else mat_ok = flux_mat<MODEL, double>(mat, mod, G, P, hq);
+        if constexpr (kDir) mat_ok = dflux_mat<MODEL, double>(mat, mod, G, dG, P, nullptr);
+        else mat_ok = flux_mat<MODEL, double>(mat, mod, G, P, nullptr);
         double *mq = Ms[id.el][q];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
