@@ -316,9 +316,10 @@ def test_block_jacobi_reduces_iterations_and_matches_point_jacobi():
 
 # ----------------------------------------------------------------------------- adjoint
 
+@pytest.mark.parametrize("name", ["nh-5x3x7-lognormal", "nh-fan-8x4"])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-8), (1, 1e-5)])
-def test_adjoint_matches_oracle(precision, tol):
-    p = CASES["nh-5x3x7-lognormal"]
+def test_adjoint_matches_oracle(precision, tol, name):
+    p = CASES[name]
     u_ref = orc.newton_solve(p, rtol=1e-13)
     dJdu = np.random.default_rng(7).standard_normal(p.n_dofs)
     g_ref, lam_ref = orc.adjoint_vjp(p, u_ref, dJdu)
