@@ -58,9 +58,19 @@ def _history(p, seed):
     return h.ravel()
 
 
+def _j2_fan():
+    """The fan prism (axis nodes with 16 elements and 51 neighbours) as a J2 problem:
+    bottom fixed, top pulled 0.01 along the axis."""
+    q = gen.nh_fan(8, 4, stretch=1.01, n_load_steps=1)
+    q.model, q.theta, q.nu, q.yield_stress = gen.J2_PLASTIC, np.full(q.n_elems, E), 0.3, SY
+    q.name = "j2-fan-8x4"
+    return q
+
+
 CASES = {
     "cylinder-5x5x6": gen.j2_cylinder(5, 6),
     "roller-3x4x5-distorted": gen.j2_roller_uniaxial(3, 4, 5, distort_seed=2),
+    "fan-8x4": _j2_fan(),
 }
 
 
