@@ -28,8 +28,12 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-def test_param_vjp_matches_oracle():
-    p = gen.simp_cantilever(8, 4, 3, distort_seed=6)
+@pytest.mark.parametrize("name", ["simp-8x4x3-distorted", "nh-fan-8x4", "nh-relabelled"])
+def test_param_vjp_matches_oracle(name):
+    p = {"simp-8x4x3-distorted": lambda: gen.simp_cantilever(8, 4, 3, distort_seed=6),
+         "nh-fan-8x4": lambda: gen.nh_fan(8, 4, n_load_steps=2, seed=6),
+         "nh-relabelled": lambda: gen.relabel(gen.nh_tensile(5, 4, 3, n_load_steps=2, seed=1, distort_seed=2),
+                                              seed=3)[0]}[name]()
     u = orc.newton_solve(p, rtol=1e-12)
     lam = np.random.default_rng(1).standard_normal(p.n_dofs)
     prob = fem.Problem(p, DEV)
