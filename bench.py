@@ -124,8 +124,8 @@ def j2_path(fem, inputs, n: int, nz: int, precond: int = 0) -> dict:
     import torch
     pj = inputs.j2_cylinder(n, nz, n_load_steps=1)
     jp = fem.Problem(pj, "cuda:0")
-    # iteration caps well above what the path needs (about 1,000 CG iterations per Newton iteration
-    # with Jacobi, 60 with the two-level preconditioner), so that a failing path ends quickly
+    # iteration caps far above what the path needs (at most about 4,000 CG iterations per load step
+    # with Jacobi, 370 with the two-level preconditioner), so that a failing path ends quickly
     jo = jp.opts(precision=fem.PREC_FP64, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-6,
                  newton_max_it=50, krylov_max_it=20000 if precond != fem.PRECOND_AMG else 2000, precond=precond)
     pname = "two-level" if precond == fem.PRECOND_AMG else "Jacobi"
