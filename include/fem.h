@@ -18,7 +18,7 @@
  *                       the von Mises surface; (eps, sigma) at every Gauss point are the
  *                       handle's history, committed after each converged load step
  * with a per-element modulus m(theta_e): theta_e itself (FEM_THETA_IDENTITY) or the
- * SIMP map emin + theta_e^p (e0 - emin) (FEM_THETA_SIMP, Sec. 3.3, Eq. (top_weak)).
+ * SIMP map emin + theta_e^p (e0 - emin) (FEM_THETA_SIMP, Sec. 3.2, Eq. (top_weak)).
  *
  * Conventions shared with callers:
  *   - HEX8 local node order 0:(0,0,0) 1:(1,0,0) 2:(1,1,0) 3:(0,1,0) 4:(0,0,1)
@@ -293,7 +293,7 @@ int fem_amg_apply(fem_handle *h, const double *u, const double *theta, const dou
                   size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------
- * SIMP compliance optimisation (Sec. 4.2): the pieces around the gradient.  The
+ * SIMP compliance optimisation (Sec. 3.2): the pieces around the gradient.  The
  * loop is: solve, compliance C = F_ext . u, dC/dtheta by the adjoint (lambda = u
  * for this self-adjoint objective) through fem_param_vjp, the sensitivity filter,
  * and one MMA step (Svanberg 1987) under the material-fraction constraint.
@@ -361,7 +361,7 @@ int fem_mma_update(int64_t n, int32_t iter, const double *x, const double *xold1
                    void *stream);
 
 /* ------------------------------------------------------------------------------
- * Full-field inference (Sec. 4.1): the source of a Poisson problem as the parameter.
+ * Full-field inference (Sec. 3.1): the source of a Poisson problem as the parameter.
  * F(theta) = M theta with M the consistent mass of the nodal source; the adjoint of
  * Eq. (full_field_inverse) gives dJ/dtheta = M lambda.
  * ---------------------------------------------------------------------------- */

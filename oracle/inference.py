@@ -3,7 +3,7 @@
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may import
 this module.  Plain numpy / scipy, FP64.
 
-Paper, Sec. 4.1 (full-field inference from sparse observations): the linear Poisson
+Paper, Sec. 3.1 (full-field inference from sparse observations): the linear Poisson
 problem -alpha Lap u = b with u = 0 on the boundary, Eq. (full_field_forward) /
 Eq. (full_field_weak); the parameter theta is the discretised source b (nodal values,
 interpolated with the shape functions, so F(theta) = M theta with the consistent mass

@@ -3,7 +3,7 @@
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may import
 this module.  Plain numpy / scipy, FP64.
 
-Paper, Sec. 4.2 (topology optimisation): compliance minimisation under the SIMP law of
+Paper, Sec. 3.2 (topology optimisation): compliance minimisation under the SIMP law of
 Eq. (top_strong)/(top_weak) with the objective of Eq. (top_inverse), a 50 % material
 constraint, a convolution filter that blurs the sensitivities, and the method of
 moving asymptotes (Svanberg 1987) as the optimiser.  The paper gives no further

@@ -118,12 +118,6 @@ int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs,
             require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
             require(d->yield_stress > 0.0 && std::isfinite(d->yield_stress), "yield_stress must be > 0");
         }
-        h = new fem_handle();
-        FEM_HIP(hipGetDevice(&h->device));
-        FEM_HIP(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device));
-        h->mat = fem::Material{d->model,   d->pmap,      d->nu,      d->bulk_ratio,
-                               d->simp_p, d->simp_emin, d->simp_e0, d->yield_stress};
-        const int64_t N = d->n_nodes * d->ndpn;
         // every node must belong to an element (otherwise its row has no diagonal)
         {
             std::vector<uint8_t> used(d->n_nodes, 0);
@@ -132,7 +126,21 @@ int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs,
                 used[d->conn[i]] = 1;
             }
             for (int64_t n = 0; n < d->n_nodes; ++n) require(used[n], "a node belongs to no element");
+            // A HEX8 element lists 8 distinct nodes: a collapsed element would send two of
+            // its node blocks to one matrix block, which the tangent gather adds once.
+            for (int64_t e = 0; e < d->n_elems; ++e) {
+                const int32_t *c = d->conn + 8 * e;
+                for (int a = 0; a < 8; ++a)
+                    for (int b = a + 1; b < 8; ++b)
+                        require(c[a] != c[b], ("element " + std::to_string(e) + " lists a node twice").c_str());
+            }
         }
+        h = new fem_handle();
+        FEM_HIP(hipGetDevice(&h->device));
+        FEM_HIP(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device));
+        h->mat = fem::Material{d->model,   d->pmap,      d->nu,      d->bulk_ratio,
+                               d->simp_p, d->simp_emin, d->simp_e0, d->yield_stress};
+        const int64_t N = d->n_nodes * d->ndpn;
         h->m.coords = static_cast<double *>(fem::dev_alloc(h, d->n_nodes * 3 * sizeof(double)));
         h->m.conn = static_cast<int32_t *>(fem::dev_alloc(h, d->n_elems * 8 * sizeof(int32_t)));
         h->m.mask = static_cast<uint8_t *>(fem::dev_alloc(h, N));

@@ -1,4 +1,4 @@
-// SIMP compliance optimisation around the gradient (Sec. 4.2): element volumes, the
+// SIMP compliance optimisation around the gradient (Sec. 3.2): element volumes, the
 // convolution filter over element centroids, a deterministic FP64 dot product and
 // the method of moving asymptotes (Svanberg 1987) for one constraint.
 //

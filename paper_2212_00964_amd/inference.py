@@ -1,4 +1,4 @@
-"""Full-field inference from sparse observations on the GPU (Sec. 4.1 of the paper).
+"""Full-field inference from sparse observations on the GPU (Sec. 3.1 of the paper).
 
 The parameter theta is the nodal source of the Poisson problem -alpha Lap u = b with
 u = 0 on the boundary.  One evaluation: F = M theta (fem_mass_apply), fem_set_load,

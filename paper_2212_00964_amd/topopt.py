@@ -1,4 +1,4 @@
-"""SIMP compliance minimisation on the GPU (Sec. 4.2 of the paper).
+"""SIMP compliance minimisation on the GPU (Sec. 3.2 of the paper).
 
 Each iteration: solve the SIMP elasticity problem (fem_newton_solve; linear, so one
 correction plus its check), the compliance C = F_ext . u (fem_dot), dC/dtheta by the

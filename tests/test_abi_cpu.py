@@ -70,3 +70,24 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_build_pattern_refuses_a_collapsed_element():
+    """An element that lists a node twice is refused with FEM_EINVAL before any device
+    work (the mesh checks run on the host first)."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_2212_00964_amd import fem
+    if not fem.library_path().exists():
+        pytest.skip("libfem.so not built")
+    coords = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [1, 1, 1]], dtype=np.float64)
+    conn = np.array([[0, 1, 2, 3, 4, 5, 6, 6]], dtype=np.int32)
+    vp = ctypes.c_void_p
+    d = fem.MeshDesc(7, 1, 3, 2, 0, 0, 0.3, 10.0, 3.0, 1e-3, 1.0, coords.ctypes.data_as(vp), conn.ctypes.data_as(vp),
+                     None, None, None, 0, None, None, 0.0)
+    h, n, nnz = vp(), ctypes.c_int64(), ctypes.c_int64()
+    rc = fem.lib().fem_build_pattern(ctypes.byref(d), ctypes.byref(h), ctypes.byref(n), ctypes.byref(nnz))
+    assert rc == -1 and not h.value
+    assert b"lists a node twice" in fem.lib().fem_last_error()

@@ -482,7 +482,7 @@ def test_neo_hookean_misfit_gradient_matches_central_differences():
 
 
 def test_taylor_test_rates():
-    """Sec. 3.2 Taylor test: |J(t + h d) - J(t)| = O(h), |... - h g.d| = O(h^2)."""
+    """Sec. 3.1 Taylor test: |J(t + h d) - J(t)| = O(h), |... - h g.d| = O(h^2)."""
     p = gen.simp_cantilever(4, 2, 2, seed=2)
     F = orc.load_vector(p)
 
