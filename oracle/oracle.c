@@ -42,6 +42,18 @@
 #define ORC_EMAXITER (-8)
 #define ORC_EBREAKDOWN (-7)
 
+/* Worker threads of the loops marked ORC_PAR below.  1, the default, runs every loop
+ * in plain sequential order, and the parity tests use the oracle that way.  More
+ * threads serve only to time the oracle on all host cores and to finish large
+ * reference solves: row loops are split by rows, inner products reduce per thread
+ * (so their rounding order differs), and the element loop of the assembly goes
+ * colour by colour (no two elements of one colour share a node, so their additions
+ * never touch the same entry).  Without OpenMP the pragmas are ignored. */
+static int orc_threads = 1;
+void orc_set_threads(int n) { orc_threads = n < 1 ? 1 : n; }
+int orc_get_threads(void) { return orc_threads; }
+#define ORC_PAR _Pragma("omp parallel for schedule(static) num_threads(orc_threads) if (orc_threads > 1)")
+
 typedef struct {
     int32_t model;     /* ORC_POISSON / ORC_ELASTIC / ORC_NEOHOOKE */
     int32_t pmap;      /* 0: modulus = theta ; 1: modulus = emin + theta^p (e0 - emin) */
@@ -522,6 +534,62 @@ int orc_transpose_perm(int64_t n_dofs, const int64_t *row_ptr, const int32_t *co
 
 /* ------------------------------------------------------------------ assembly (Alg. 1) */
 
+/* Greedy colouring of the elements: element e takes the smallest colour that no
+ * earlier element sharing a node with it has taken.  Writes the elements of colour c,
+ * ascending, to elems[ptr[c] .. ptr[c+1]) and returns the number of colours, or -1
+ * when 64 colours do not suffice. */
+int orc_element_colours(int64_t n_nodes, int64_t n_elems, const int32_t *conn, int64_t ptr[65], int64_t *elems) {
+    uint64_t *used = calloc(n_nodes > 0 ? n_nodes : 1, sizeof(uint64_t));
+    uint8_t *colour = malloc(n_elems > 0 ? n_elems : 1);
+    int nc = 0;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        uint64_t taken = 0;
+        for (int a = 0; a < 8; ++a) taken |= used[conn[8 * e + a]];
+        if (taken == ~(uint64_t)0) {
+            free(used);
+            free(colour);
+            return -1;
+        }
+        int c = 0;
+        while (taken & ((uint64_t)1 << c)) ++c;
+        colour[e] = (uint8_t)c;
+        for (int a = 0; a < 8; ++a) used[conn[8 * e + a]] |= (uint64_t)1 << c;
+        if (c + 1 > nc) nc = c + 1;
+    }
+    for (int c = 0; c <= 64; ++c) ptr[c] = 0;
+    for (int64_t e = 0; e < n_elems; ++e) ptr[colour[e] + 1]++;
+    for (int c = 0; c < 64; ++c) ptr[c + 1] += ptr[c];
+    int64_t fill[64];
+    for (int c = 0; c < 64; ++c) fill[c] = ptr[c];
+    for (int64_t e = 0; e < n_elems; ++e) elems[fill[colour[e]]++] = e;
+    free(used);
+    free(colour);
+    return nc;
+}
+
+/* One pass of Alg. 1's loop body for element e: r_e into r, K_e into the CSR values
+ * through the slot map (either output may be NULL).  Ke is scratch of Nd*Nd doubles. */
+static int assemble_element(int64_t e, int ndpn, const double *coords, const int32_t *conn, const orc_material *m,
+                            const double *theta, const double *u, const int32_t *slot, double *r, double *values,
+                            double *Ke) {
+    int Nd = 8 * ndpn;
+    double X[8][3], Ue[24], re[24];
+    double mod = orc_modulus(m, theta[e]);
+    gather_element(coords, conn, e, ndpn, u, X, Ue);
+    if (r) {
+        int rc = orc_element_residual(m, mod, ndpn, X, Ue, re);
+        if (rc) return rc;
+        for (int p = 0; p < Nd; ++p) r[(int64_t)ndpn * conn[8 * e + p / ndpn] + p % ndpn] += re[p];
+    }
+    if (values) {
+        int rc = orc_element_stiffness(m, mod, ndpn, X, Ue, Ke);
+        if (rc) return rc;
+        for (int p = 0; p < Nd; ++p)
+            for (int q = 0; q < Nd; ++q) values[slot[((int64_t)e * Nd + p) * Nd + q]] += Ke[p * Nd + q];
+    }
+    return ORC_OK;
+}
+
 /* Residual r = R_int(u; theta) - F and (optionally) tangent values in CSR order,
  * literally as Alg. 1: loop over elements, form r_e and K_e, add them into the
  * globals through the slot map.  Then Dirichlet rows/columns are eliminated
@@ -534,41 +602,49 @@ int orc_assemble(int64_t n_nodes, int64_t n_elems, int ndpn, const double *coord
     if (r)
         for (int64_t d = 0; d < N; ++d) r[d] = 0.0;
     if (values) memset(values, 0, (size_t)row_ptr[N] * sizeof(double));
-    double X[8][3], Ue[24], re[24];
-    double *Ke = malloc((size_t)Nd * Nd * sizeof(double));
-    for (int64_t e = 0; e < n_elems; ++e) {
-        double mod = orc_modulus(m, theta[e]);
-        gather_element(coords, conn, e, ndpn, u, X, Ue);
-        if (r) {
-            int rc = orc_element_residual(m, mod, ndpn, X, Ue, re);
-            if (rc) {
+    int rc = ORC_OK;
+    if (orc_threads <= 1) {
+        double *Ke = malloc((size_t)Nd * Nd * sizeof(double));
+        for (int64_t e = 0; e < n_elems && rc == ORC_OK; ++e)
+            rc = assemble_element(e, ndpn, coords, conn, m, theta, u, slot, r, values, Ke);
+        free(Ke);
+    } else {
+        int64_t ptr[65];
+        int64_t *elems = malloc((n_elems > 0 ? n_elems : 1) * sizeof(int64_t));
+        int nc = orc_element_colours(n_nodes, n_elems, conn, ptr, elems);
+        if (nc < 0) rc = ORC_EMAXITER;
+        for (int c = 0; c < nc && rc == ORC_OK; ++c) {
+#pragma omp parallel num_threads(orc_threads)
+            {
+                double *Ke = malloc((size_t)Nd * Nd * sizeof(double));
+                int rc_t = ORC_OK;
+#pragma omp for schedule(static)
+                for (int64_t j = ptr[c]; j < ptr[c + 1]; ++j)
+                    if (rc_t == ORC_OK)
+                        rc_t = assemble_element(elems[j], ndpn, coords, conn, m, theta, u, slot, r, values, Ke);
                 free(Ke);
-                return rc;
+                if (rc_t != ORC_OK) {
+#pragma omp critical
+                    rc = rc_t;
+                }
             }
-            for (int p = 0; p < Nd; ++p) r[(int64_t)ndpn * conn[8 * e + p / ndpn] + p % ndpn] += re[p];
         }
-        if (values) {
-            int rc = orc_element_stiffness(m, mod, ndpn, X, Ue, Ke);
-            if (rc) {
-                free(Ke);
-                return rc;
-            }
-            for (int p = 0; p < Nd; ++p)
-                for (int q = 0; q < Nd; ++q) values[slot[((int64_t)e * Nd + p) * Nd + q]] += Ke[p * Nd + q];
-        }
+        free(elems);
     }
-    free(Ke);
+    if (rc) return rc;
     if (r)
         for (int64_t d = 0; d < N; ++d) {
             if (F) r[d] -= F[d];
             if (mask && mask[d]) r[d] = 0.0;
         }
-    if (values && mask)
+    if (values && mask) {
+        ORC_PAR
         for (int64_t i = 0; i < N; ++i)
             for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
                 int64_t j = col_idx[k];
                 if (mask[i] || mask[j]) values[k] = (i == j) ? 1.0 : 0.0;
             }
+    }
     return ORC_OK;
 }
 
@@ -576,6 +652,7 @@ int orc_assemble(int64_t n_nodes, int64_t n_elems, int ndpn, const double *coord
 
 void orc_spmv(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const double *values, const double *x,
               double *y) {
+    ORC_PAR
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += values[k] * x[col_idx[k]];
@@ -585,6 +662,7 @@ void orc_spmv(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const d
 
 static double dot(int64_t n, const double *a, const double *b) {
     double s = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : s) num_threads(orc_threads) if (orc_threads > 1)
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
 }
@@ -595,14 +673,17 @@ int orc_pcg(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const dou
             double *x, double rtol, int maxit, int *its_out, double *relres_out) {
     double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double)), *p = malloc(n * sizeof(double)),
            *q = malloc(n * sizeof(double)), *dinv = malloc(n * sizeof(double));
+    ORC_PAR
     for (int64_t i = 0; i < n; ++i) {
         int64_t k = csr_find(row_ptr, col_idx, i, (int32_t)i);
         dinv[i] = 1.0 / values[k];
     }
     orc_spmv(n, row_ptr, col_idx, values, x, q);
+    ORC_PAR
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     double bn = sqrt(dot(n, b, b));
     if (bn == 0.0) bn = 1.0;
+    ORC_PAR
     for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
     memcpy(p, z, n * sizeof(double));
     double rz = dot(n, r, z), rn = sqrt(dot(n, r, r));
@@ -614,14 +695,17 @@ int orc_pcg(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const dou
         }
         orc_spmv(n, row_ptr, col_idx, values, p, q);
         double alpha = rz / dot(n, p, q);
+        ORC_PAR
         for (int64_t i = 0; i < n; ++i) {
             x[i] += alpha * p[i];
             r[i] -= alpha * q[i];
         }
+        ORC_PAR
         for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
         double rz_new = dot(n, r, z);
         double beta = rz_new / rz;
         rz = rz_new;
+        ORC_PAR
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         rn = sqrt(dot(n, r, r));
         ++it;
@@ -648,11 +732,13 @@ int orc_bicgstab(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, cons
     double *r = malloc(n * sizeof(double)), *rh = malloc(n * sizeof(double)), *p = calloc(n, sizeof(double)),
            *v = calloc(n, sizeof(double)), *ph = malloc(n * sizeof(double)), *s = malloc(n * sizeof(double)),
            *sh = malloc(n * sizeof(double)), *t = malloc(n * sizeof(double)), *dinv = malloc(n * sizeof(double));
+    ORC_PAR
     for (int64_t i = 0; i < n; ++i) {
         int64_t k = csr_find(row_ptr, col_idx, i, (int32_t)i);
         dinv[i] = 1.0 / values[k];
     }
     orc_spmv(n, row_ptr, col_idx, values, x, t);
+    ORC_PAR
     for (int64_t i = 0; i < n; ++i) {
         r[i] = b[i] - t[i];
         rh[i] = r[i];
@@ -673,12 +759,14 @@ int orc_bicgstab(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, cons
         }
         double beta = (rho_new / rho) * (alpha / omega);
         rho = rho_new;
+        ORC_PAR
         for (int64_t i = 0; i < n; ++i) {
             p[i] = r[i] + beta * (p[i] - omega * v[i]);
             ph[i] = dinv[i] * p[i];
         }
         orc_spmv(n, row_ptr, col_idx, values, ph, v);
         alpha = rho / dot(n, rh, v);
+        ORC_PAR
         for (int64_t i = 0; i < n; ++i) {
             s[i] = r[i] - alpha * v[i];
             sh[i] = dinv[i] * s[i];
@@ -686,6 +774,7 @@ int orc_bicgstab(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, cons
         orc_spmv(n, row_ptr, col_idx, values, sh, t);
         double tt = dot(n, t, t);
         omega = tt > 0.0 ? dot(n, t, s) / tt : 0.0;
+        ORC_PAR
         for (int64_t i = 0; i < n; ++i) {
             x[i] += alpha * ph[i] + omega * sh[i];
             r[i] = s[i] - omega * t[i];
@@ -719,11 +808,17 @@ int orc_bicgstab(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, cons
  * do not depend on theta, so they are skipped. */
 int orc_vjp_theta(int64_t n_elems, int ndpn, const double *coords, const int32_t *conn, const orc_material *m,
                   const double *theta, const double *u, const double *lam, const uint8_t *mask, double *g) {
-    double X[8][3], Ue[24], re[24];
+    int rc_all = ORC_OK;
+    ORC_PAR
     for (int64_t e = 0; e < n_elems; ++e) {
+        double X[8][3], Ue[24], re[24];
         gather_element(coords, conn, e, ndpn, u, X, Ue);
         int rc = orc_element_residual(m, 1.0, ndpn, X, Ue, re);
-        if (rc) return rc;
+        if (rc) {
+#pragma omp critical
+            rc_all = rc;
+            continue;
+        }
         double s = 0.0;
         for (int p = 0; p < 8 * ndpn; ++p) {
             int64_t d = (int64_t)ndpn * conn[8 * e + p / ndpn] + p % ndpn;
@@ -732,7 +827,7 @@ int orc_vjp_theta(int64_t n_elems, int ndpn, const double *coords, const int32_t
         }
         g[e] = -orc_dmodulus(m, theta[e]) * s;
     }
-    return ORC_OK;
+    return rc_all;
 }
 
 /* Per-element residual and stiffness for a list of elements (used to check sampled
@@ -740,21 +835,22 @@ int orc_vjp_theta(int64_t n_elems, int ndpn, const double *coords, const int32_t
 int orc_elements_dense(int64_t n_sel, const int64_t *sel, int ndpn, const double *coords, const int32_t *conn,
                        const orc_material *m, const double *theta, const double *u, double *re_out, double *Ke_out) {
     int Nd = 8 * ndpn;
-    double X[8][3], Ue[24];
+    int rc_all = ORC_OK;
+    ORC_PAR
     for (int64_t s = 0; s < n_sel; ++s) {
+        double X[8][3], Ue[24];
         int64_t e = sel[s];
         double mod = orc_modulus(m, theta[e]);
         gather_element(coords, conn, e, ndpn, u, X, Ue);
-        if (re_out) {
-            int rc = orc_element_residual(m, mod, ndpn, X, Ue, re_out + s * Nd);
-            if (rc) return rc;
-        }
-        if (Ke_out) {
-            int rc = orc_element_stiffness(m, mod, ndpn, X, Ue, Ke_out + s * Nd * Nd);
-            if (rc) return rc;
+        int rc = ORC_OK;
+        if (re_out) rc = orc_element_residual(m, mod, ndpn, X, Ue, re_out + s * Nd);
+        if (!rc && Ke_out) rc = orc_element_stiffness(m, mod, ndpn, X, Ue, Ke_out + s * Nd * Nd);
+        if (rc) {
+#pragma omp critical
+            rc_all = rc;
         }
     }
-    return ORC_OK;
+    return rc_all;
 }
 
 /* ------------------------------------------------------------------ perfect J2 plasticity

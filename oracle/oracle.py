@@ -85,6 +85,9 @@ def _load():
                                 ctypes.POINTER(ctypes.c_double)]),
         "orc_vjp_theta": (_int, [_i64, _int, _dp, _i32p, M, _dp, _dp, _dp, _vp, _dp]),
         "orc_elements_dense": (_int, [_i64, _i64p, _int, _dp, _i32p, M, _dp, _vp, _vp, _vp]),
+        "orc_set_threads": (None, [_int]),
+        "orc_get_threads": (_int, []),
+        "orc_element_colours": (_int, [_i64, _i64, _i32p, _i64p, _i64p]),
         "orc_j2_stress": (_int, [M, ctypes.c_double, _dp, _dp, _dp, ctypes.POINTER(_int)]),
         "orc_j2_tangent": (_int, [M, ctypes.c_double, _dp, _dp, _dp]),
         "orc_j2_assemble": (_int, [_i64, _i64, _dp, _i32p, M, _dp, _dp, _dp, _vp, _vp, _i64p, _i32p, _i32p, _vp,
@@ -107,6 +110,33 @@ def lib():
     if _lib is None:
         _lib = _load()
     return _lib
+
+
+class threads:
+    """Runs the oracle's loops on n host threads inside the block (1 outside it: the
+    sequential oracle).  Assembly then adds elements colour by colour and inner
+    products reduce per thread, so results agree with the sequential ones to rounding."""
+
+    def __init__(self, n: int):
+        self.n = max(1, int(n))
+
+    def __enter__(self):
+        self.prev = lib().orc_get_threads()
+        lib().orc_set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_threads(self.prev)
+
+
+def element_colours(prob):
+    """Greedy element colouring used by the threaded assembly: (ptr[65], elems)."""
+    ptr = np.zeros(65, dtype=np.int64)
+    elems = np.zeros(max(prob.n_elems, 1), dtype=np.int64)
+    nc = lib().orc_element_colours(prob.n_nodes, prob.n_elems, _c(prob.conn, np.int32), ptr, elems)
+    if nc < 0:
+        raise OracleError(nc, "element colouring (more than 64 colours)")
+    return ptr[:nc + 1].copy(), elems[:prob.n_elems]
 
 
 def _ptr(a):
