@@ -34,10 +34,17 @@
  * DEVICE pointers owned by the caller (e.g. torch tensors on the same GPU) and
  * must stay valid until the call's work on `stream` has finished.  The handle
  * owns its own device copies of the mesh and the sparsity structure (allocated
- * in fem_build_pattern, released by fem_destroy).  Scratch memory for assembly
- * and solves is a caller-provided device `workspace` of fem_workspace_bytes(),
- * 256-byte aligned (FEM_EINVAL otherwise; torch allocations are).
- * `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ * in fem_build_pattern, released by fem_destroy): node graph, row pointers, the
+ * element-to-block maps and small reduction buffers, about 1.4 GB for a
+ * 1M-element mesh.  They are built on the host from the mesh, live as long as the
+ * handle, and are not exposed as caller buffers (a caller-allocated form would add
+ * a size query and a fill call per array for no gain in reuse).  Only three setup
+ * calls allocate device memory: fem_build_pattern, fem_amg_setup and
+ * fem_filter_setup.  Every other call allocates nothing: scratch memory for
+ * assembly and solves is a caller-provided device `workspace` of
+ * fem_workspace_bytes(), 256-byte aligned (FEM_EINVAL otherwise; torch
+ * allocations are).  `stream` is a hipStream_t passed as void* (NULL = the
+ * default stream).
  */
 #ifndef FEM_H
 #define FEM_H
@@ -90,7 +97,7 @@ enum { FEM_KRYLOV_CG = 0, FEM_KRYLOV_BICGSTAB = 1 };
  * The paper names the Jacobi-preconditioned solver as the bottleneck (Sec. 5, item 2);
  * this is the stronger preconditioner built on that remark.  The handle builds the
  * aggregates and prolongator once (first use) and keeps them with the coarse operator
- * of the latest tangent; see fem_amg_export / fem_amg_apply below. */
+ * of the latest tangent; see fem_amg_setup / fem_amg_export / fem_amg_apply below. */
 enum { FEM_PRECOND_JACOBI = 0, FEM_PRECOND_BLOCK_JACOBI = 1, FEM_PRECOND_AMG = 2 };
 
 typedef struct fem_handle fem_handle;
@@ -139,6 +146,12 @@ typedef struct {
     int32_t precond;        /* FEM_PRECOND_JACOBI, FEM_PRECOND_BLOCK_JACOBI or FEM_PRECOND_AMG (CG only) */
     int32_t amg_smooth_degree; /* FEM_PRECOND_AMG: Chebyshev steps of each fine smoothing (1..64) */
     int32_t amg_coarse_degree; /* FEM_PRECOND_AMG: Chebyshev steps on the coarse operator (1..64) */
+    int32_t max_bisections; /* load-step recovery of fem_newton_solve (0 = off, at most 30): when a
+                               load step fails with FEM_EBREAKDOWN, FEM_EMAXITER, FEM_EDIVERGED,
+                               FEM_EINVERTED or FEM_ENAN, u is restored to the start of the step
+                               and the remaining increment is halved, at most this many times per
+                               load step */
+    int32_t reserved_opts;
 } fem_solve_opts;
 
 #define FEM_MAX_HIST 64
@@ -156,6 +169,11 @@ typedef struct {
     int32_t krylov_its[FEM_MAX_HIST];     /* Krylov iterations of each correction solve */
     double residual_hist[FEM_MAX_HIST];   /* ||r_free|| before each correction */
     double krylov_relres[FEM_MAX_HIST];   /* final recursive ||r||/||b|| of each correction solve */
+    int32_t bisections;       /* load-step halvings taken by the recovery (opts.max_bisections) */
+    int32_t reserved_stats;
+    double iter_ms[FEM_MAX_HIST];         /* fem_newton_solve: wall time of each Newton iteration, from
+                                             its right-hand side to the residual norm after the update
+                                             (the first iteration of a load step includes the lifting) */
 } fem_solve_stats;
 
 /* Message of the last failure on this thread ("" if none).  Never NULL. */
@@ -164,7 +182,7 @@ const char *fem_last_error(void);
 /* Fills *opts with defaults: FP64, BiCGSTAB, 1 load step, newton_max_it 30,
  * newton_rtol 1e-10, atol 0, krylov_rtol 1e-6, krylov_max_it 20000,
  * check_every 16, adjoint_rtol 1e-10, adjoint_max_refine 20, profile off,
- * newton_fixed_its 0. */
+ * newton_fixed_its 0, Jacobi, amg degrees 1 / 16, max_bisections 0. */
 int fem_default_opts(fem_solve_opts *opts);
 
 /* Builds the handle: uploads the mesh, computes the external load vector
@@ -203,14 +221,29 @@ int fem_workspace_bytes(fem_handle *h, const fem_solve_opts *opts, size_t *bytes
  *   residual [N] FP64 (may be NULL): r = R_int(u; theta) - F_ext, Dirichlet entries 0;
  *   values [fem_values_count(layout)] (may be NULL): K(u) in `values_layout`,
  *   FEM_F32 or FEM_F64, with the symmetric Dirichlet elimination.
- *   u [N] FP64, theta [n_elems] FP64.
- * Blocks until the kernels finish and reports FEM_EMESH / FEM_EINVERTED / FEM_ENAN. */
+ *   u [N] FP64, theta [n_elems] FP64; workspace of fem_workspace_bytes(h, NULL).
+ * Asynchronous on `stream`: the call checks its arguments (errors returned at once),
+ * clears the handle's status word and enqueues the kernels.  Conditions the kernels
+ * detect (det J <= 0, det F <= 0, NaN) raise bits in that word; fem_check reports
+ * them after the work has finished. */
 int fem_assemble(fem_handle *h, const double *u, const double *theta, double *residual, void *values,
                  int32_t values_dtype, int32_t values_layout, void *workspace, size_t workspace_bytes, void *stream);
 
-/* y = alpha * op(K) x + beta * y with op(K) = K or K^T (transpose != 0; for
- * FEM_LAYOUT_SYM_BLOCK both are K); values, x and y all of `dtype`; products and
- * sums in that dtype.  With beta == 0, y is not read.  Asynchronous on `stream`. */
+/* Waits for `stream` and reports what the kernels of the enqueue-only calls
+ * (fem_assemble) found since they cleared the status word: FEM_EMESH (det J <= 0 at a
+ * Gauss point), FEM_EINVERTED (det F <= 0), FEM_ENAN, or FEM_OK.  A reported condition
+ * is cleared.  Blocks. */
+int fem_check(fem_handle *h, void *stream);
+
+/* The matrix-vector product inside the Jacobi-preconditioned Krylov solver (Sec. 5,
+ * item 2, which names that solver as the cost of the forward problem; the transposed
+ * form is the operator of the adjoint equation, Sec. 3, Eq. (adjoint_PDE)):
+ * y = alpha * op(K) x + beta * y with op(K) = K or K^T (transpose != 0; for
+ * FEM_LAYOUT_SYM_BLOCK both are K).  values [fem_values_count(layout)] in `layout`
+ * (as written by fem_assemble), x and y [N], all of `dtype` (FEM_F32 or FEM_F64) on the
+ * device; products and sums in that dtype.  With beta == 0, y is not read.  x and y
+ * must not overlap.  Asynchronous on `stream`; FEM_EINVAL for bad enums or NULL
+ * pointers. */
 int fem_spmv(fem_handle *h, const void *values, int32_t dtype, int32_t layout, int32_t transpose, const void *x,
              void *y, double alpha, double beta, void *stream);
 
@@ -270,9 +303,15 @@ int fem_average_stress(fem_handle *h, double *out, void *stream);
  * Two-level preconditioner (FEM_PRECOND_AMG): its parts, for inspection and tests.
  * ---------------------------------------------------------------------------- */
 
-/* Builds the aggregation and prolongator if needed and returns, to the host, the
- * number of aggregates and of coarse ncoarse x ncoarse blocks (ncoarse = 6, or 1 when
- * ndpn = 1).  Synchronous. */
+/* Setup of the two-level preconditioner (a setup call, like fem_build_pattern): builds
+ * the node aggregates and the rigid-body-mode prolongator on the host and allocates
+ * the handle's device arrays for them, the coarse operator and its vectors.  Once per
+ * handle (later calls return at once); needed before any call with FEM_PRECOND_AMG
+ * (FEM_EINVAL otherwise).  Synchronous. */
+int fem_amg_setup(fem_handle *h);
+
+/* The number of aggregates and of coarse ncoarse x ncoarse blocks (ncoarse = 6, or 1
+ * when ndpn = 1), to the host.  FEM_EINVAL before fem_amg_setup. */
 int fem_amg_sizes(fem_handle *h, int64_t *n_aggregates, int64_t *n_coarse_blocks);
 
 /* Copies to caller DEVICE buffers (any may be NULL): the aggregate of every node

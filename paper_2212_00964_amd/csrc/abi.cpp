@@ -49,6 +49,7 @@ void validate_opts(const fem_solve_opts *o) {
     require(o->newton_rtol >= 0.0 && o->newton_atol >= 0.0 && o->adjoint_rtol >= 0.0, "opts tolerances");
     require(o->adjoint_max_refine >= 1, "opts.adjoint_max_refine must be >= 1");
     require(o->newton_fixed_its >= 0, "opts.newton_fixed_its must be >= 0");
+    require(o->max_bisections >= 0 && o->max_bisections <= 30, "opts.max_bisections must be in [0, 30]");
     require(o->precond == FEM_PRECOND_JACOBI || o->precond == FEM_PRECOND_BLOCK_JACOBI ||
                 o->precond == FEM_PRECOND_AMG,
             "opts.precond");
@@ -57,6 +58,11 @@ void validate_opts(const fem_solve_opts *o) {
         require(o->amg_smooth_degree >= 1 && o->amg_smooth_degree <= 64, "opts.amg_smooth_degree must be in [1, 64]");
         require(o->amg_coarse_degree >= 1 && o->amg_coarse_degree <= 64, "opts.amg_coarse_degree must be in [1, 64]");
     }
+}
+
+void require_amg_ready(const fem_handle *h, const fem_solve_opts *o) {
+    if (o->precond == FEM_PRECOND_AMG && h->g.N > 0)
+        require(h->amg != nullptr, "FEM_PRECOND_AMG needs fem_amg_setup on the handle first");
 }
 
 void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, size_t bytes) {
@@ -68,6 +74,8 @@ void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, siz
 }
 
 }  // namespace
+
+int fem::run_guarded(const std::function<void()> &f) { return guarded(f); }
 
 extern "C" {
 
@@ -244,7 +252,22 @@ int fem_assemble(fem_handle *h, const double *u, const double *theta, double *re
                 fem::launch_tangent<double>(h, u, theta, static_cast<double *>(ke), static_cast<double *>(values), nullptr, s,
                                             ly);
         }
-        fem::check_status(h, s);
+        // enqueue only: the kernels' error bits stay in the status word for fem_check
+    });
+}
+
+int fem_check(fem_handle *h, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        bind_device(h);
+        hipStream_t s = as_stream(stream);
+        try {
+            fem::check_status(h, s);
+        } catch (const fem::Error &) {
+            fem::reset_status(h, s);  // reported once
+            FEM_HIP(hipStreamSynchronize(s));
+            throw;
+        }
     });
 }
 
@@ -299,6 +322,7 @@ int fem_newton_solve(fem_handle *h, double *u, const double *theta, const double
         if (stats) std::memset(stats, 0, sizeof(*stats));
         if (h->g.N == 0) return;
         require(u && theta && dirichlet_values, "u, theta and dirichlet_values must be non-NULL");
+        require_amg_ready(h, opts);
         check_workspace(h, opts, workspace, workspace_bytes);
         bind_device(h);
         fem::newton_solve(h, u, theta, dirichlet_values, *opts, stats, workspace, workspace_bytes, as_stream(stream));
@@ -315,6 +339,7 @@ int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const d
         if (h->g.N == 0) return;
         require(h->mat.model != FEM_J2_PLASTIC, "the adjoint is not defined for FEM_J2_PLASTIC");
         require(u && theta && dJdu && vjp_theta, "u, theta, dJdu and vjp_theta must be non-NULL");
+        require_amg_ready(h, opts);
         check_workspace(h, opts, workspace, workspace_bytes);
         bind_device(h);
         fem::adjoint_vjp(h, u, theta, dJdu, vjp_theta, lambda_out, *opts, stats, workspace, workspace_bytes,
@@ -347,11 +372,18 @@ int fem_average_stress(fem_handle *h, double *out, void *stream) {
     });
 }
 
+int fem_amg_setup(fem_handle *h) {
+    return guarded([&] {
+        require(h != nullptr, "handle is NULL");
+        bind_device(h);
+        fem::amg_setup(h);
+    });
+}
+
 int fem_amg_sizes(fem_handle *h, int64_t *n_aggregates, int64_t *n_coarse_blocks) {
     return guarded([&] {
         require(h != nullptr && n_aggregates != nullptr && n_coarse_blocks != nullptr, "arguments must be non-NULL");
-        bind_device(h);
-        fem::amg_setup(h);
+        require(h->amg != nullptr, "fem_amg_setup has not been called");
         *n_aggregates = h->amg->na;
         *n_coarse_blocks = h->amg->nbc;
     });
@@ -360,8 +392,8 @@ int fem_amg_sizes(fem_handle *h, int64_t *n_aggregates, int64_t *n_coarse_blocks
 int fem_amg_export(fem_handle *h, int32_t *agg, double *P, int64_t *coarse_ptr, int32_t *coarse_col) {
     return guarded([&] {
         require(h != nullptr, "handle is NULL");
+        require(h->amg != nullptr, "fem_amg_setup has not been called");
         bind_device(h);
-        fem::amg_setup(h);
         const fem::Amg &a = *h->amg;
         const int64_t Nn = h->g.Nn;
         if (agg && Nn) FEM_HIP(hipMemcpy(agg, a.agg, Nn * sizeof(int32_t), hipMemcpyDeviceToDevice));
@@ -382,6 +414,7 @@ int fem_amg_apply(fem_handle *h, const double *u, const double *theta, const dou
         require(opts->precond == FEM_PRECOND_AMG, "opts.precond must be FEM_PRECOND_AMG");
         if (h->g.N == 0) return;
         require(u && theta && r && z && r != z, "u, theta, r and z must be non-NULL (r and z distinct)");
+        require_amg_ready(h, opts);
         check_workspace(h, opts, workspace, workspace_bytes);
         bind_device(h);
         fem::amg_apply_once(h, u, theta, r, z, *opts, lmax_out, coarse_values, workspace, workspace_bytes,

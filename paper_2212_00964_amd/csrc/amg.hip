@@ -35,7 +35,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWavesPerBlock = kThreads / 64;
-constexpr int kRedGrid = 1024;
 constexpr int kPowerSteps = 12;
 constexpr double kLmaxSafety = 1.2;
 constexpr double kChebRatio = 30.0;
@@ -768,7 +767,7 @@ void amg_destroy(fem_handle *h) {
 template <typename T>
 void amg_refresh(fem_handle *h, const T *values, const T *dinv, int precision, int smooth_degree, int coarse_degree,
                  hipStream_t s) {
-    amg_setup(h);
+    if (!h->amg) throw Error(FEM_EINVAL, "FEM_PRECOND_AMG needs fem_amg_setup on the handle first");
     Amg &a = *h->amg;
     const Graph &g = h->g;
     AmgView<T> v = view<T>(h);

@@ -1120,15 +1120,13 @@ void launch_j2_commit(const fem_handle *h, const double *u, const double *theta,
     FEM_HIP(hipGetLastError());
 }
 
+size_t j2_partials_count(int64_t n_elems) { return size_t(grid_for(n_elems, kElemsPerBlock)) * 7; }
+
 void j2_average_stress(fem_handle *h, double out[6], hipStream_t s) {
     const Graph &g = h->g;
     for (int c = 0; c < 6; ++c) out[c] = 0.0;
     if (g.Ne == 0) return;
     const unsigned grid = grid_for(g.Ne, kElemsPerBlock);
-    if (!h->hist_partials) {
-        FEM_HIP(hipMalloc(reinterpret_cast<void **>(&h->hist_partials), size_t(grid) * 7 * sizeof(double)));
-        h->allocations.push_back(h->hist_partials);
-    }
     hipLaunchKernelGGL(k_j2_average, dim3(grid), dim3(kThreads), 0, s, g.Ne, h->m.coords, h->m.conn, h->hist,
                        h->hist_partials);
     FEM_HIP(hipGetLastError());

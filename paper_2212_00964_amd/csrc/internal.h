@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -19,6 +20,11 @@ struct Error : std::runtime_error {
     Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// Runs f, translating a thrown Error (or any other exception) into its status code
+// and the thread's last-error message; FEM_OK clears the message.  Every ABI entry
+// point runs its body through this.
+int run_guarded(const std::function<void()> &f);
+
 #define FEM_HIP(call)                                                                                        \
     do {                                                                                                     \
         hipError_t e_ = (call);                                                                              \
@@ -26,6 +32,9 @@ struct Error : std::runtime_error {
             throw ::fem::Error(e_ == hipErrorOutOfMemory ? FEM_ENOMEM : FEM_EHIP,                            \
                                std::string(#call " failed: ") + hipGetErrorString(e_));                      \
     } while (0)
+
+// Blocks of the grid-stride reduction kernels (one FP64 partial per block).
+constexpr int kRedGrid = 1024;
 
 // Bits of the device status word raised by kernels.
 enum : int { ST_MESH = 1, ST_INVERTED = 2, ST_NAN = 4, ST_BREAKDOWN = 8 };
@@ -149,10 +158,10 @@ struct fem_handle {
     int num_cus = 256;                        // compute units of the device
     std::vector<void *> allocations;          // device allocations owned by the handle
     fem::Filter filter;                       // fem_filter_setup (owns its allocations)
-    double *red_partials = nullptr;           // reduction partials of fem_element_volumes (lazy)
+    double *red_partials = nullptr;           // [kRedGrid] reduction partials (fem_element_volumes, fem_set_load)
     double *hist = nullptr;                   // J2 history [Ne*8*12] (eps, sigma per Gauss point)
-    double *hist_partials = nullptr;          // per-block partials of fem_average_stress (lazy)
-    fem::Amg *amg = nullptr;                  // two-level preconditioner (lazy)
+    double *hist_partials = nullptr;          // per-block partials of fem_average_stress (J2)
+    fem::Amg *amg = nullptr;                  // two-level preconditioner (fem_amg_setup)
 };
 
 namespace fem {
@@ -185,6 +194,8 @@ void launch_vjp(const fem_handle *h, const double *u, const double *theta, const
 // J2: commit the history at u (after a converged load step); volume-averaged stress.
 void launch_j2_commit(const fem_handle *h, const double *u, const double *theta, hipStream_t s);
 void j2_average_stress(fem_handle *h, double out[6], hipStream_t s);
+// Doubles of the per-block partials of j2_average_stress (allocated with the history).
+size_t j2_partials_count(int64_t n_elems);
 template <typename T>
 void launch_extract_dinv(const fem_handle *h, const T *values, T *dinv, hipStream_t s, int layout = LAYOUT_CSR);
 

@@ -290,7 +290,9 @@ void build_load_vector(fem_handle *h, const fem_mesh_desc *d) {
         const size_t bytes = size_t(d->n_elems) * 96 * sizeof(double);
         h->hist = static_cast<double *>(dev_alloc(h, bytes));
         FEM_HIP(hipMemset(h->hist, 0, bytes == 0 ? 256 : bytes));
+        h->hist_partials = static_cast<double *>(dev_alloc(h, j2_partials_count(d->n_elems) * sizeof(double)));
     }
+    h->red_partials = static_cast<double *>(dev_alloc(h, kRedGrid * sizeof(double)));
 }
 
 }  // namespace fem

@@ -68,6 +68,7 @@ static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_
     w.u0 = c.take<double>(N);
     w.res64 = c.take<double>(N);
     w.lam64 = c.take<double>(N);
+    w.ustep = c.take<double>(N);
     w.rscr = c.take<double>(g.Ne * 8 * g.nd);
     w.ke = need_ke ? static_cast<void *>(c.take<T>(g.Ne * 64 * g.nd * g.nd)) : nullptr;
     w.values = c.take<T>(kSolverLayout == LAYOUT_SYM ? g.nnzb_up * g.nd * g.nd : g.nnz);
@@ -184,6 +185,11 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
         if (hs.converged) break;
         if (hs.breakdown) {
             if (hs.breakdown == 2) throw Error(FEM_ENAN, "NaN/Inf in a Krylov inner product");
+            // CG's breakdown is a direction with p.Kp <= 0: the tangent is not positive
+            // definite, so no CG iterate can be trusted
+            if (cg)
+                throw Error(FEM_EBREAKDOWN, "CG met non-positive curvature p.Kp <= 0 at iteration " +
+                                                std::to_string(hs.its) + " (the tangent is not positive definite)");
             if (hs.its == 0) throw Error(FEM_EBREAKDOWN, "Krylov breakdown before the first update");
             break;  // keep the last iterate; the outer loop measures its true residual
         }
@@ -249,10 +255,80 @@ static int correction(fem_handle *h, SolveWork &w, double *u, const double *thet
     return kits;
 }
 
-// Newton's method with incremental loading.  The first iteration of a load step
+// One load step of Newton's method, to the load factor lam.  The first iteration
 // carries the Dirichlet increment D through the tangent at the previous state
 // (du_D = D, K_ff du_f = -r_f - K_fD D); the following iterations solve
 // K(u) du = -r(u) with the Dirichlet rows and columns eliminated.
+template <typename T>
+static void load_step(fem_handle *h, SolveWork &w, double *u, const double *theta, const double *gD, double lam,
+                      int k, const fem_solve_opts &o, fem_solve_stats *st, hipStream_t s) {
+    const int64_t N = h->g.N;
+    auto t0 = clk::now();
+    auto t_it = t0;  // start of the current Newton iteration
+    // wall time of the Newton iteration whose correction was recorded last
+    auto record_iter = [&] {
+        if (st && st->n_hist >= 1 && st->n_hist <= FEM_MAX_HIST) st->iter_ms[st->n_hist - 1] = ms_since(t_it);
+    };
+    launch_dirichlet_increment(h, u, w.u0, gD, lam, w.res64, s);
+    launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
+    launch_lift(h, u, theta, w.res64, w.rscr, w.lam64, s);
+    launch_neg_sum(w.r64, w.lam64, w.r64, N, s);  // predictor right-hand side
+    const double bn = norm2(h, w.r64, w, s);
+    check_status(h, s);
+    if (st) st->ms_residual += ms_since(t0);
+    if (!std::isfinite(bn)) throw Error(FEM_ENAN, "non-finite Newton right-hand side");
+    const double ref = std::max(bn, lam * h->m.fext_norm);
+    const double tol = std::max(o.newton_rtol * ref, o.newton_atol);
+    if (st) {
+        st->initial_residual = bn;
+        st->load_steps = k;
+    }
+    const int fixed = o.newton_fixed_its;
+    int it = 0;
+    if (bn > tol || fixed > 0) {
+        if (o.newton_max_it < 1) throw Error(FEM_EMAXITER, "newton_max_it = 0");
+        launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), 1.0, N, s);
+        correction<T>(h, w, u, theta, o, st, bn, s);
+        ++it;
+    }
+    launch_set_dirichlet(h, u, w.u0, gD, lam, s);
+    t0 = clk::now();
+    launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
+    double rn = norm2(h, w.r64, w, s);
+    check_status(h, s);
+    if (st) st->ms_residual += ms_since(t0);
+    if (it > 0) record_iter();
+    while (fixed > 0 ? it < fixed : !(rn <= tol)) {
+        if (!std::isfinite(rn)) throw Error(FEM_ENAN, "non-finite Newton residual");
+        if (rn > 1e8 * std::max(ref, 1e-300)) throw Error(FEM_EDIVERGED, "Newton residual diverged");
+        if (fixed == 0 && it >= o.newton_max_it)
+            throw Error(FEM_EMAXITER, "Newton did not converge in load step " + std::to_string(k) +
+                                          " (|r| = " + sci(rn) + ", tol = " + sci(tol) + ")");
+        t_it = clk::now();
+        launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), -1.0, N, s);
+        correction<T>(h, w, u, theta, o, st, rn, s);
+        t0 = clk::now();
+        launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
+        rn = norm2(h, w.r64, w, s);
+        check_status(h, s);
+        if (st) st->ms_residual += ms_since(t0);
+        record_iter();
+        ++it;
+    }
+    if (st) st->final_residual = rn;
+    launch_j2_commit(h, u, theta, s);  // path-dependent laws: the converged step becomes the history
+}
+
+// Failures a smaller load increment can cure.
+static bool recoverable(int code) {
+    return code == FEM_EBREAKDOWN || code == FEM_EMAXITER || code == FEM_EDIVERGED || code == FEM_EINVERTED ||
+           code == FEM_ENAN;
+}
+
+// Newton's method with incremental loading: load step k of n moves the load factor to
+// k/n.  With opts.max_bisections > 0 a failed step is retried from its starting state
+// with half the remaining increment (at most max_bisections halvings per load step);
+// every converged sub-step commits the history of path-dependent laws.
 template <typename T>
 static void newton_impl(fem_handle *h, double *u, const double *theta, const double *gD, const fem_solve_opts &o,
                         fem_solve_stats *st, void *ws, size_t wsb, hipStream_t s) {
@@ -264,54 +340,33 @@ static void newton_impl(fem_handle *h, double *u, const double *theta, const dou
     reset_status(h, s);
     FEM_HIP(hipMemcpyAsync(w.u0, u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     const int nsteps = std::max(1, o.n_load_steps);
+    double lam_done = 0.0;
     for (int k = 1; k <= nsteps; ++k) {
-        const double lam = double(k) / nsteps;
-        auto t0 = clk::now();
-        launch_dirichlet_increment(h, u, w.u0, gD, lam, w.res64, s);
-        launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
-        launch_lift(h, u, theta, w.res64, w.rscr, w.lam64, s);
-        launch_neg_sum(w.r64, w.lam64, w.r64, N, s);  // predictor right-hand side
-        const double bn = norm2(h, w.r64, w, s);
-        check_status(h, s);
-        if (st) st->ms_residual += ms_since(t0);
-        if (!std::isfinite(bn)) throw Error(FEM_ENAN, "non-finite Newton right-hand side");
-        const double ref = std::max(bn, lam * h->m.fext_norm);
-        const double tol = std::max(o.newton_rtol * ref, o.newton_atol);
-        if (st) {
-            st->initial_residual = bn;
-            st->load_steps = k;
+        const double lam_k = double(k) / nsteps;
+        if (o.max_bisections == 0) {
+            load_step<T>(h, w, u, theta, gD, lam_k, k, o, st, s);
+            lam_done = lam_k;
+            continue;
         }
-        const int fixed = o.newton_fixed_its;
-        int it = 0;
-        if (bn > tol || fixed > 0) {
-            if (o.newton_max_it < 1) throw Error(FEM_EMAXITER, "newton_max_it = 0");
-            launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), 1.0, N, s);
-            correction<T>(h, w, u, theta, o, st, bn, s);
-            ++it;
+        double inc = lam_k - lam_done;
+        int halvings = 0;
+        while (lam_done < lam_k) {
+            // the last sub-step lands exactly on lam_k
+            const double target = (lam_done + inc >= lam_k - 1e-12 * inc) ? lam_k : lam_done + inc;
+            FEM_HIP(hipMemcpyAsync(w.ustep, u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            try {
+                load_step<T>(h, w, u, theta, gD, target, k, o, st, s);
+                lam_done = target;
+            } catch (const Error &e) {
+                if (!recoverable(e.code) || halvings >= o.max_bisections) throw;
+                FEM_HIP(hipMemcpyAsync(u, w.ustep, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+                reset_status(h, s);
+                FEM_HIP(hipStreamSynchronize(s));
+                inc *= 0.5;
+                ++halvings;
+                if (st) st->bisections++;
+            }
         }
-        launch_set_dirichlet(h, u, w.u0, gD, lam, s);
-        t0 = clk::now();
-        launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
-        double rn = norm2(h, w.r64, w, s);
-        check_status(h, s);
-        if (st) st->ms_residual += ms_since(t0);
-        while (fixed > 0 ? it < fixed : !(rn <= tol)) {
-            if (!std::isfinite(rn)) throw Error(FEM_ENAN, "non-finite Newton residual");
-            if (rn > 1e8 * std::max(ref, 1e-300)) throw Error(FEM_EDIVERGED, "Newton residual diverged");
-            if (fixed == 0 && it >= o.newton_max_it)
-                throw Error(FEM_EMAXITER, "Newton did not converge in load step " + std::to_string(k) +
-                                              " (|r| = " + sci(rn) + ", tol = " + sci(tol) + ")");
-            launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), -1.0, N, s);
-            correction<T>(h, w, u, theta, o, st, rn, s);
-            t0 = clk::now();
-            launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
-            rn = norm2(h, w.r64, w, s);
-            check_status(h, s);
-            if (st) st->ms_residual += ms_since(t0);
-            ++it;
-        }
-        if (st) st->final_residual = rn;
-        launch_j2_commit(h, u, theta, s);  // path-dependent laws: the converged step becomes the history
     }
     if (st) st->ms_total += ms_since(t_all);
 }

@@ -17,7 +17,6 @@ namespace fem {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRedGrid = 1024;  // blocks of every reduction kernel here
 
 inline unsigned grid_for(int64_t n) { return unsigned(std::max<int64_t>(1, (n + kThreads - 1) / kThreads)); }
 
@@ -222,11 +221,10 @@ double host_sum(const double *partials_dev, double *pinned, hipStream_t s) {
     return t;
 }
 
-// Pinned read-back slots for the partials, one buffer per host thread, allocated on
-// first use and kept for the life of the process.
-double *pinned_partials() {
-    static thread_local double *p = nullptr;
-    if (!p) FEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&p), kRedGrid * sizeof(double)));
+// Host read-back slots for the partials, one array per host thread (ordinary host
+// memory: the calls that read partials back allocate nothing).
+double *readback_partials() {
+    static thread_local double p[kRedGrid];
     return p;
 }
 
@@ -241,13 +239,9 @@ void element_volumes(fem_handle *h, double *vol, bool normalized, hipStream_t s)
     FEM_HIP(hipGetLastError());
     if (!normalized) return;
     // total by the deterministic reduction, then v_e / total
-    if (!h->red_partials) {
-        FEM_HIP(hipMalloc(reinterpret_cast<void **>(&h->red_partials), kRedGrid * sizeof(double)));
-        h->allocations.push_back(h->red_partials);
-    }
     hipLaunchKernelGGL(k_sum, dim3(kRedGrid), dim3(kThreads), 0, s, h->g.Ne, vol, h->red_partials);
     FEM_HIP(hipGetLastError());
-    const double total = host_sum(h->red_partials, pinned_partials(), s);
+    const double total = host_sum(h->red_partials, readback_partials(), s);
     hipLaunchKernelGGL(k_scale, dim3(grid_for(h->g.Ne)), dim3(kThreads), 0, s, h->g.Ne, 1.0 / total, vol);
     FEM_HIP(hipGetLastError());
     FEM_HIP(hipStreamSynchronize(s));
@@ -353,7 +347,7 @@ double dot(const double *a, const double *b, int64_t n, void *ws, hipStream_t s)
     double *partials = static_cast<double *>(ws);
     hipLaunchKernelGGL(k_dot, dim3(kRedGrid), dim3(kThreads), 0, s, n, a, b, partials);
     FEM_HIP(hipGetLastError());
-    return host_sum(partials, pinned_partials(), s);
+    return host_sum(partials, readback_partials(), s);
 }
 
 void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
@@ -368,20 +362,16 @@ double obs_misfit(int64_t n, int64_t n_obs, const int64_t *idx, const double *ob
     if (n) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kThreads), 0, s, n, 0.0, dJdu);
     hipLaunchKernelGGL(k_obs_misfit, dim3(kRedGrid), dim3(kThreads), 0, s, n_obs, idx, obs, u, dJdu, partials);
     FEM_HIP(hipGetLastError());
-    return host_sum(partials, pinned_partials(), s);
+    return host_sum(partials, readback_partials(), s);
 }
 
 void set_load(fem_handle *h, const double *f, hipStream_t s) {
     const int64_t N = h->g.N;
     if (N == 0) return;
     FEM_HIP(hipMemcpyAsync(h->m.fext, f, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (!h->red_partials) {
-        FEM_HIP(hipMalloc(reinterpret_cast<void **>(&h->red_partials), kRedGrid * sizeof(double)));
-        h->allocations.push_back(h->red_partials);
-    }
     hipLaunchKernelGGL(k_sumsq_free, dim3(kRedGrid), dim3(kThreads), 0, s, N, h->m.fext, h->m.mask, h->red_partials);
     FEM_HIP(hipGetLastError());
-    h->m.fext_norm = std::sqrt(host_sum(h->red_partials, pinned_partials(), s));
+    h->m.fext_norm = std::sqrt(host_sum(h->red_partials, readback_partials(), s));
 }
 
 double mma_update(int64_t n, int iter, const double *x, const double *xold1, const double *xold2, const double *df0,
@@ -393,7 +383,7 @@ double mma_update(int64_t n, int iter, const double *x, const double *xold1, con
                 reinterpret_cast<double *>(base + 2 * vb), reinterpret_cast<double *>(base + 3 * vb),
                 reinterpret_cast<double *>(base + 4 * vb), reinterpret_cast<double *>(base + 5 * vb)};
     double *partials = reinterpret_cast<double *>(base + 6 * vb);
-    double *pin = pinned_partials();
+    double *pin = readback_partials();
     hipLaunchKernelGGL(k_mma_prep, dim3(kRedGrid), dim3(kThreads), 0, s, n, iter, x, xold1, xold2, df0, df1, low, upp,
                        o, A, partials);
     FEM_HIP(hipGetLastError());

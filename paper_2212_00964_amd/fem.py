@@ -58,7 +58,8 @@ class SolveOpts(ctypes.Structure):
                 ("krylov_max_it", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("adjoint_rtol", ctypes.c_double), ("adjoint_max_refine", ctypes.c_int32),
                 ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("amg_smooth_degree", ctypes.c_int32), ("amg_coarse_degree", ctypes.c_int32)]
+                ("amg_smooth_degree", ctypes.c_int32), ("amg_coarse_degree", ctypes.c_int32),
+                ("max_bisections", ctypes.c_int32), ("reserved_opts", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -68,10 +69,12 @@ class SolveStats(ctypes.Structure):
                 ("ms_assemble", ctypes.c_double), ("ms_krylov", ctypes.c_double), ("ms_vjp", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("spmv_calls", ctypes.c_int32), ("krylov_unconverged", ctypes.c_int32),
                 ("spmv_ms_total", ctypes.c_double), ("krylov_its", ctypes.c_int32 * MAX_HIST),
-                ("residual_hist", ctypes.c_double * MAX_HIST), ("krylov_relres", ctypes.c_double * MAX_HIST)]
+                ("residual_hist", ctypes.c_double * MAX_HIST), ("krylov_relres", ctypes.c_double * MAX_HIST),
+                ("bisections", ctypes.c_int32), ("reserved_stats", ctypes.c_int32),
+                ("iter_ms", ctypes.c_double * MAX_HIST)]
 
     def as_dict(self) -> dict:
-        arrays = ("krylov_its", "residual_hist", "krylov_relres")
+        arrays = ("krylov_its", "residual_hist", "krylov_relres", "iter_ms")
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in arrays}
         for k in arrays:
             d[k] = list(getattr(self, k)[:self.n_hist])
@@ -87,9 +90,9 @@ class MmaOpts(ctypes.Structure):
 
 # Names, in the order the header declares them (checked by the CPU test-suite).
 EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
-           "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_spmv",
+           "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_check", "fem_spmv",
            "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_history_copy", "fem_average_stress",
-           "fem_amg_sizes", "fem_amg_export", "fem_amg_apply", "fem_param_vjp", "fem_element_volumes",
+           "fem_amg_setup", "fem_amg_sizes", "fem_amg_export", "fem_amg_apply", "fem_param_vjp", "fem_element_volumes",
            "fem_filter_setup", "fem_filter_apply", "fem_vector_workspace_bytes", "fem_dot", "fem_mma_default_opts",
            "fem_mma_update", "fem_mass_apply", "fem_set_load", "fem_axpby", "fem_obs_misfit"]
 
@@ -120,12 +123,14 @@ def lib():
         "fem_load_vector": (ctypes.c_int, [vp, vp, vp]),
         "fem_workspace_bytes": (ctypes.c_int, [vp, P(SolveOpts), P(sz)]),
         "fem_assemble": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]),
+        "fem_check": (ctypes.c_int, [vp, vp]),
         "fem_spmv": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, dbl, dbl, vp]),
         "fem_apply_tangent": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "fem_newton_solve": (ctypes.c_int, [vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
         "fem_adjoint_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, P(SolveOpts), P(SolveStats), vp, sz, vp]),
         "fem_history_copy": (ctypes.c_int, [vp, vp, i32, vp]),
         "fem_average_stress": (ctypes.c_int, [vp, P(dbl), vp]),
+        "fem_amg_setup": (ctypes.c_int, [vp]),
         "fem_amg_sizes": (ctypes.c_int, [vp, P(i64), P(i64)]),
         "fem_amg_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fem_amg_apply": (ctypes.c_int, [vp, vp, vp, vp, vp, P(SolveOpts), P(dbl), vp, vp, sz, vp]),
@@ -330,7 +335,7 @@ class Problem:
         return c.value
 
     def assemble(self, u, theta=None, residual: bool = True, values_dtype: Optional[torch.dtype] = torch.float64,
-                 layout: int = LAYOUT_CSR):
+                 layout: int = LAYOUT_CSR, check: bool = True):
         u = self._f64(u, self.n_dofs)
         theta = self.theta if theta is None else self._f64(theta, self.n_elems)
         r = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device) if residual else None
@@ -342,7 +347,13 @@ class Problem:
         ws = self.workspace(None)
         _check(lib().fem_assemble(self.handle, _ptr(u), _ptr(theta), _ptr(r), _ptr(vals), dt, layout, _ptr(ws),
                                   ws.numel(), _stream()))
+        if check:
+            self.check()
         return r, vals
+
+    def check(self):
+        """Waits for the stream and raises what the enqueue-only kernels found (fem_check)."""
+        _check(lib().fem_check(self.handle, _stream()))
 
     def spmv(self, values: torch.Tensor, x: torch.Tensor, transpose: bool = False, alpha: float = 1.0,
              beta: float = 0.0, y: Optional[torch.Tensor] = None, layout: int = LAYOUT_CSR) -> torch.Tensor:
@@ -395,8 +406,17 @@ class Problem:
         _check(lib().fem_average_stress(self.handle, out, _stream()))
         return list(out)
 
+    def amg_setup(self):
+        """Builds the two-level preconditioner's aggregates and prolongator (fem_amg_setup, once)."""
+        _check(lib().fem_amg_setup(self.handle))
+
+    def _ready(self, opts):
+        if opts.precond == PRECOND_AMG:
+            self.amg_setup()
+
     def amg_sizes(self):
         """(aggregates, coarse blocks) of the two-level preconditioner (fem_amg_sizes)."""
+        self.amg_setup()
         na, nb = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().fem_amg_sizes(self.handle, ctypes.byref(na), ctypes.byref(nb)))
         return na.value, nb.value
@@ -430,6 +450,7 @@ class Problem:
         z = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         cv = torch.empty(max(nb * nc * nc, 1), dtype=torch.float64, device=self.device)
         lm = (ctypes.c_double * 2)()
+        self._ready(opts)
         ws = self.workspace(opts)
         _check(lib().fem_amg_apply(self.handle, _ptr(u), _ptr(theta), _ptr(r), _ptr(z), ctypes.byref(opts), lm,
                                    _ptr(cv), _ptr(ws), ws.numel(), _stream()))
@@ -472,6 +493,7 @@ class Problem:
              else self._f64(u0, self.n_dofs).clone())
         g = self.dirichlet_values if dirichlet_values is None else self._f64(dirichlet_values, self.n_dofs)
         st = SolveStats()
+        self._ready(opts)
         ws = self.workspace(opts)
         _check(lib().fem_newton_solve(self.handle, _ptr(u), _ptr(theta), _ptr(g), ctypes.byref(opts),
                                       ctypes.byref(st), _ptr(ws), ws.numel(), _stream()), st)
@@ -485,6 +507,7 @@ class Problem:
         g = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
         lam = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device) if want_lambda else None
         st = SolveStats()
+        self._ready(opts)
         ws = self.workspace(opts)
         _check(lib().fem_adjoint_vjp(self.handle, _ptr(u), _ptr(theta), _ptr(dJdu), _ptr(g), _ptr(lam),
                                      ctypes.byref(opts), ctypes.byref(st), _ptr(ws), ws.numel(), _stream()), st)

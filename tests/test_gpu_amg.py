@@ -14,6 +14,7 @@ import torch
 from oracle import amg
 from oracle import oracle as orc
 from paper_2212_00964_amd import inputs as gen
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -100,9 +101,9 @@ def test_coarse_operator_bounds_and_application_match_oracle(name, precision):
     z, lm, cv = prob.amg_apply(u, r, precision=precision)
     ex = prob.amg_export()
     tol = 1e-11 if precision == 0 else 1e-4
-    assert rel(_coarse_dense(ex, host(cv)), M.Ac.toarray()) <= (1e-12 if precision == 0 else 1e-5)
+    assert_parity(_coarse_dense(ex, host(cv)), M.Ac.toarray(), (1e-12 if precision == 0 else 1e-5))
     assert abs(lm[0] - M.lmax) <= tol * M.lmax and abs(lm[1] - M.lmax_c) <= tol * M.lmax_c
-    assert rel(host(z), M.apply(r)) <= tol
+    assert_parity(host(z), M.apply(r), tol)
     prob.close()
 
 
@@ -123,11 +124,11 @@ def test_newton_with_two_level_preconditioner_matches_oracle(name, precision):
     if precision == 0:
         u, st = prob.newton_solve(precision=0, krylov=fem.CG, precond=fem.PRECOND_AMG, newton_rtol=1e-12,
                                   krylov_rtol=1e-10)
-        assert rel(host(u), u_ref) <= 1e-10, st.as_dict()
+        assert_parity(host(u), u_ref, 1e-10, st.as_dict())
     else:
         u, st = prob.newton_solve(precision=1, krylov=fem.CG, precond=fem.PRECOND_AMG, newton_rtol=1e-10,
                                   krylov_rtol=1e-5)
-        assert rel(host(u), u_ref) <= 1e-6, st.as_dict()
+        assert_parity(host(u), u_ref, 1e-6, st.as_dict())
     prob.close()
 
 
@@ -142,8 +143,8 @@ def test_adjoint_with_two_level_preconditioner_matches_oracle(precision):
                                   adjoint_rtol=1e-11 if precision == 0 else 1e-9,
                                   krylov_rtol=1e-8 if precision == 0 else 1e-3)
     tol = 1e-8 if precision == 0 else 1e-5
-    assert rel(host(lam), lam_ref) <= tol, st.as_dict()
-    assert rel(host(g), g_ref) <= tol
+    assert_parity(host(lam), lam_ref, tol, st.as_dict())
+    assert_parity(host(g), g_ref, tol)
     prob.close()
 
 
@@ -165,4 +166,28 @@ def test_two_level_option_errors():
         with pytest.raises(fem.FemError) as ei:
             prob.newton_solve(precond=fem.PRECOND_AMG, **kw)
         assert ei.value.name == "FEM_EINVAL"
+    prob.close()
+
+
+def test_two_level_needs_its_setup_call():
+    """FEM_PRECOND_AMG through the C ABI on a handle without fem_amg_setup is refused
+    (the setup is the one call that allocates the preconditioner's memory)."""
+    import ctypes
+    p = CASES["poisson-9-distorted"]
+    prob = fem.Problem(p, DEV)
+    L = fem.lib()
+    na, nb = ctypes.c_int64(), ctypes.c_int64()
+    assert L.fem_amg_sizes(prob.handle, ctypes.byref(na), ctypes.byref(nb)) == -1
+    opts = prob.opts(krylov=fem.CG, precond=fem.PRECOND_AMG)
+    u = torch.zeros(p.n_dofs, dtype=torch.float64, device=DEV)
+    ws = prob.workspace(opts)
+    st = fem.SolveStats()
+    rc = L.fem_newton_solve(prob.handle, fem._ptr(u), fem._ptr(prob.theta), fem._ptr(prob.dirichlet_values),
+                            ctypes.byref(opts), ctypes.byref(st), fem._ptr(ws), ws.numel(), fem._stream())
+    assert rc == -1 and b"fem_amg_setup" in L.fem_last_error()
+    assert L.fem_amg_setup(prob.handle) == 0
+    assert L.fem_amg_setup(prob.handle) == 0  # once per handle
+    rc = L.fem_newton_solve(prob.handle, fem._ptr(u), fem._ptr(prob.theta), fem._ptr(prob.dirichlet_values),
+                            ctypes.byref(opts), ctypes.byref(st), fem._ptr(ws), ws.numel(), fem._stream())
+    assert rc == 0, L.fem_last_error()
     prob.close()

@@ -8,6 +8,7 @@ from paper_2212_00964_amd import inputs as gen
 from paper_2212_00964_amd.inference import SourceInference, lbfgs
 from oracle import inference as inf
 from oracle import oracle as orc
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -36,7 +37,7 @@ def test_mass_apply_matches_oracle(case):
         p = gen.relabel(gen.cantilever(5, 3, 4, distort_seed=1), seed=2)[0]
     x = np.random.default_rng(5).standard_normal(p.n_dofs)
     prob = fem.Problem(p, DEV)
-    assert rel(host(prob.mass_apply(x)), inf.mass_apply(p, x)) <= 1e-13
+    assert_parity(host(prob.mass_apply(x)), inf.mass_apply(p, x), 1e-13)
     prob.close()
 
 
@@ -74,10 +75,10 @@ def test_forward_value_and_gradient_match_oracle():
     fun = SourceInference(prob, obs, u_true[obs])
     T = torch.as_tensor(theta, device=DEV)
     u = fun.solve(T)
-    assert rel(host(u), fun_o.solve(theta)) <= 1e-10
+    assert_parity(host(u), fun_o.solve(theta), 1e-10)
     J, g = fun.value_and_grad(T)
     assert abs(J - J_o) <= 1e-9 * J_o
-    assert rel(host(g), g_o) <= 1e-9
+    assert_parity(host(g), g_o, 1e-9)
     prob.close()
 
 
@@ -89,7 +90,7 @@ def test_lbfgs_iterations_match_oracle():
     hx, hJ = lbfgs(fun, torch.zeros(p.n_nodes, dtype=torch.float64, device=DEV), 6)
     np.testing.assert_allclose(hJ, hJ_o, rtol=1e-6)
     for a, b in zip(hx, hx_o):
-        assert rel(host(a), b) <= 1e-6
+        assert_parity(host(a), b, 1e-6)
     prob.close()
 
 

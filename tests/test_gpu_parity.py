@@ -16,6 +16,7 @@ import torch
 
 from oracle import oracle as orc
 from paper_2212_00964_amd import inputs as gen
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +94,7 @@ def test_pattern_bit_exact_poisson_8cube():
 def test_load_vector(name):
     p = CASES[name]
     prob = fem.Problem(p, DEV)
-    assert rel(host(prob.load_vector()), orc.load_vector(p)) <= 1e-14
+    assert_parity(host(prob.load_vector()), orc.load_vector(p), 1e-14)
     prob.close()
 
 
@@ -111,10 +112,10 @@ def test_assembly_fp64_and_fp32(name):
     r_ref, K_ref = orc.assemble(p, pat, u, F=F)
     prob = fem.Problem(p, DEV)
     r, K = prob.assemble(u)
-    assert rel(host(r), r_ref) <= 1e-13
-    assert rel(host(K), K_ref) <= 1e-13
+    assert_parity(host(r), r_ref, 1e-13)
+    assert_parity(host(K), K_ref, 1e-13)
     _, K32 = prob.assemble(u, residual=False, values_dtype=torch.float32)
-    assert rel(host(K32), K_ref) <= 2e-6
+    assert_parity(host(K32), K_ref, 2e-6)
     prob.close()
 
 
@@ -137,11 +138,11 @@ def test_spmv(name, dtype, transpose):
     y = torch.as_tensor(y0, dtype=dtype, device=DEV)
     prob.spmv(K, torch.as_tensor(x, dtype=dtype, device=DEV), transpose=transpose, alpha=0.7, beta=-1.3, y=y)
     tol = 1e-13 if dtype == torch.float64 else 5e-6
-    assert rel(host(y), expect) <= tol
+    assert_parity(host(y), expect, tol)
     # beta = 0 must not read y (fill it with NaN)
     y = torch.full((p.n_dofs,), float("nan"), dtype=dtype, device=DEV)
     prob.spmv(K, torch.as_tensor(x, dtype=dtype, device=DEV), transpose=transpose, y=y)
-    assert rel(host(y), A @ x) <= tol
+    assert_parity(host(y), A @ x, tol)
     prob.close()
 
 
@@ -188,7 +189,7 @@ def test_wide_numbering_takes_32bit_indices():
     for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 5e-6)):
         _, K = prob.assemble(np.zeros(q.n_dofs), residual=False, values_dtype=dtype)
         y = prob.spmv(K, torch.as_tensor(x, dtype=dtype, device=DEV))
-        assert rel(host(y), A @ x) <= tol
+        assert_parity(host(y), A @ x, tol)
     for kry in (fem.CG, fem.BICGSTAB):
         u, st = prob.newton_solve(precision=fem.PREC_FP64, krylov=kry, newton_rtol=1e-11, krylov_rtol=1e-11)
         r, _ = orc.assemble(q, pat, host(u), F=F, matrix=False)
@@ -209,14 +210,14 @@ def test_symmetric_block_layout_assembly_and_spmv(name, dtype):
     assert Ks.numel() < prob.nnz
     full = sym_to_csr(pat, host(Ks).astype(np.float64), p.ndpn)
     tol = 1e-13 if dtype == torch.float64 else 2e-6
-    assert rel(full, K_ref) <= tol
+    assert_parity(full, K_ref, tol)
     x = np.random.default_rng(8).standard_normal(p.n_dofs)
     y0 = np.random.default_rng(9).standard_normal(p.n_dofs)
     y = torch.as_tensor(y0, dtype=dtype, device=DEV)
     prob.spmv(Ks, torch.as_tensor(x, dtype=dtype, device=DEV), alpha=-0.5, beta=2.0, y=y,
               layout=fem.LAYOUT_SYM_BLOCK)
     expect = -0.5 * (pat.matrix(K_ref) @ x) + 2.0 * y0
-    assert rel(host(y), expect) <= (1e-13 if dtype == torch.float64 else 5e-6)
+    assert_parity(host(y), expect, (1e-13 if dtype == torch.float64 else 5e-6))
     prob.close()
 
 
@@ -230,7 +231,7 @@ def test_apply_tangent_matches_assembled_operator(name):
     v = np.random.default_rng(5).standard_normal(p.n_dofs)
     prob = fem.Problem(p, DEV)
     y = prob.apply_tangent(u, v)
-    assert rel(host(y), pat.matrix(K_ref) @ v) <= 1e-13
+    assert_parity(host(y), pat.matrix(K_ref) @ v, 1e-13)
     prob.close()
 
 
@@ -252,7 +253,7 @@ def test_newton_fp64_matches_oracle(name):
     u_ref = orc.newton_solve(p, linear=lin, rtol=1e-13)
     prob = fem.Problem(p, DEV)
     u, st = prob.newton_solve(precision=fem.PREC_FP64, newton_rtol=1e-13, krylov_rtol=1e-8)
-    assert rel(host(u), u_ref) <= 1e-10, st.as_dict()
+    assert_parity(host(u), u_ref, 1e-10, st.as_dict())
     prob.close()
 
 
@@ -262,7 +263,7 @@ def test_newton_mixed_matches_oracle(name):
     u_ref = orc.newton_solve(p, linear=lin, rtol=1e-13)
     prob = fem.Problem(p, DEV)
     u, st = prob.newton_solve(precision=fem.PREC_MIXED, newton_rtol=1e-10, krylov_rtol=1e-5)
-    assert rel(host(u), u_ref) <= 1e-6, st.as_dict()
+    assert_parity(host(u), u_ref, 1e-6, st.as_dict())
     prob.close()
 
 
@@ -299,7 +300,7 @@ def test_newton_block_jacobi_matches_oracle(name, krylov, precision):
     fp64 = precision == fem.PREC_FP64
     u, st = prob.newton_solve(precision=precision, krylov=krylov, precond=fem.PRECOND_BLOCK_JACOBI,
                               newton_rtol=1e-13 if fp64 else 1e-10, krylov_rtol=1e-8 if fp64 else 1e-5)
-    assert rel(host(u), u_ref) <= (1e-10 if fp64 else 1e-6), st.as_dict()
+    assert_parity(host(u), u_ref, (1e-10 if fp64 else 1e-6), st.as_dict())
     prob.close()
 
 
@@ -309,7 +310,7 @@ def test_block_jacobi_reduces_iterations_and_matches_point_jacobi():
     u1, s1 = prob.newton_solve(precision=fem.PREC_FP64, krylov=fem.CG, newton_rtol=1e-12, krylov_rtol=1e-6)
     u2, s2 = prob.newton_solve(precision=fem.PREC_FP64, krylov=fem.CG, newton_rtol=1e-12, krylov_rtol=1e-6,
                                precond=fem.PRECOND_BLOCK_JACOBI)
-    assert rel(host(u2), host(u1)) <= 1e-9
+    assert_parity(host(u2), host(u1), 1e-9)
     assert s2.krylov_its_total < s1.krylov_its_total, (s1.krylov_its_total, s2.krylov_its_total)
     prob.close()
 
@@ -326,13 +327,13 @@ def test_adjoint_matches_oracle(precision, tol, name):
     prob = fem.Problem(p, DEV)
     g, lam, st = prob.adjoint_vjp(u_ref, dJdu, precision=precision, adjoint_rtol=1e-11 if precision == 0 else 1e-9,
                                   krylov_rtol=1e-8 if precision == 0 else 1e-5)
-    assert rel(host(lam), lam_ref) <= tol, st.as_dict()
-    assert rel(host(g), g_ref) <= tol
+    assert_parity(host(lam), lam_ref, tol, st.as_dict())
+    assert_parity(host(g), g_ref, tol)
     g2, lam2, st2 = prob.adjoint_vjp(u_ref, dJdu, precision=precision, precond=fem.PRECOND_BLOCK_JACOBI,
                                      adjoint_rtol=1e-11 if precision == 0 else 1e-9,
                                      krylov_rtol=1e-8 if precision == 0 else 1e-5)
-    assert rel(host(lam2), lam_ref) <= tol, st2.as_dict()
-    assert rel(host(g2), g_ref) <= tol
+    assert_parity(host(lam2), lam_ref, tol, st2.as_dict())
+    assert_parity(host(g2), g_ref, tol)
     prob.close()
 
 
@@ -344,14 +345,14 @@ def test_simp_gradient_closed_form_and_fd():
     u, _ = prob.newton_solve(opts=opts)
     g, lam, _ = prob.adjoint_vjp(u, torch.as_tensor(F, device=DEV), opts=opts)
     u_h, g_h, lam_h = host(u), host(g), host(lam)
-    assert rel(lam_h, u_h) <= 1e-9  # compliance is self-adjoint
+    assert_parity(lam_h, u_h, 1e-9)  # compliance is self-adjoint
     # closed form from the oracle's unit-modulus element matrices at the GPU's state
     unit = gen.simp_cantilever(9, 4, 3)
     unit.pmap, unit.theta = gen.THETA_IDENTITY, np.ones(p.n_elems)
     _, Ke = orc.elements_dense(unit, np.arange(p.n_elems), u_h, residual=False)
     closed = np.array([-3 * p.theta[e] ** 2 * (1 - 1e-3) * (u_h[orc.element_dofs(p, e)] @ Ke[e] @ u_h[orc.element_dofs(p, e)])
                        for e in range(p.n_elems)])
-    assert rel(g_h, closed) <= 1e-9
+    assert_parity(g_h, closed, 1e-9)
     # central finite differences of J(theta) = F.U(theta), J from the oracle's solves
     def J(theta):
         return F @ orc.newton_solve(p, theta=theta, rtol=1e-12)
@@ -376,7 +377,7 @@ def test_autograd_function_backward_is_adjoint():
     loss.backward()
     u_ref = orc.newton_solve(p, rtol=1e-13)
     g_ref, _ = orc.adjoint_vjp(p, u_ref, w.cpu().numpy())
-    assert rel(host(theta.grad), g_ref + p.theta) <= 1e-8
+    assert_parity(host(theta.grad), g_ref + p.theta, 1e-8)
     prob.close()
 
 
@@ -485,4 +486,69 @@ def test_empty_mesh_is_a_no_op():
     assert prob.n_dofs == 0 and prob.nnz == 0
     u, st = prob.newton_solve()
     assert u.numel() == 0 and st.newton_its == 0
+    prob.close()
+
+
+def test_assemble_is_enqueue_only_and_check_reports_once():
+    """fem_assemble returns once its kernels are enqueued; what they find is reported
+    by fem_check after the stream has finished, once."""
+    p = gen.cantilever(3, 2, 2)
+    p.coords = p.coords.copy()
+    p.coords[p.conn[0, 6]] = p.coords[p.conn[0, 0]] - 0.5
+    prob = fem.Problem(p, DEV)
+    prob.assemble(np.zeros(p.n_dofs), check=False)  # no error yet: nothing has been read back
+    with pytest.raises(fem.FemError) as ei:
+        prob.check()
+    assert ei.value.name == "FEM_EMESH"
+    prob.check()  # reported once
+    prob.close()
+    q = CASES["nh-5x3x7-lognormal"]
+    prob = fem.Problem(q, DEV)
+    r, K = prob.assemble(_state(q), check=False)
+    prob.check()
+    r2, K2 = prob.assemble(_state(q))
+    assert torch.equal(r, r2) and torch.equal(K, K2)
+    prob.close()
+
+
+# ----------------------------------------------------------------------------- load-step recovery
+
+def test_newton_bisects_a_load_step_that_fails():
+    """One load step to stretch 1.2 needs n Newton iterations; allowed n - 1 it fails, and
+    with the load-step recovery it is cut into sub-steps (each needing fewer) and
+    reaches the oracle's solution."""
+    p = gen.nh_tensile(4, 4, 3, n_load_steps=5, seed=1, distort_seed=2)
+    u_ref = orc.newton_solve(p, rtol=1e-13)
+    prob = fem.Problem(p, DEV)
+    kw = dict(precision=fem.PREC_FP64, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-13, krylov_rtol=1e-10)
+    u_full, st_full = prob.newton_solve(**kw)
+    n = st_full.newton_its
+    assert n >= 3, st_full.as_dict()
+    assert_parity(host(u_full), u_ref, 1e-10, st_full.as_dict())
+    with pytest.raises(fem.FemError) as ei:
+        prob.newton_solve(newton_max_it=n - 1, **kw)
+    assert ei.value.name == "FEM_EMAXITER"
+    u, st = prob.newton_solve(newton_max_it=n - 1, max_bisections=8, **kw)
+    assert st.bisections >= 1, st.as_dict()
+    assert_parity(host(u), u_ref, 1e-10, st.as_dict())
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", [fem.PREC_FP64, fem.PREC_MIXED])
+def test_cg_reports_non_positive_curvature(precision):
+    """A negative modulus makes the tangent negative definite: CG must stop with
+    FEM_EBREAKDOWN instead of returning an iterate; the recovery halves the step up to
+    its limit and then reports the same error."""
+    p = gen.cantilever(4, 3, 2)
+    prob = fem.Problem(p, DEV)
+    theta = -np.ones(p.n_elems)
+    with pytest.raises(fem.FemError) as ei:
+        prob.newton_solve(theta=theta, precision=precision, krylov=fem.CG)
+    assert ei.value.name == "FEM_EBREAKDOWN"
+    with pytest.raises(fem.FemError) as ei:
+        prob.newton_solve(theta=theta, precision=precision, krylov=fem.CG, max_bisections=2)
+    assert ei.value.name == "FEM_EBREAKDOWN"
+    assert ei.value.stats.bisections == 2
+    u, _ = prob.newton_solve(precision=precision, krylov=fem.CG)  # the handle still solves afterwards
+    assert torch.isfinite(u).all()
     prob.close()
