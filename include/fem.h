@@ -229,8 +229,21 @@ int fem_workspace_bytes(fem_handle *h, const fem_solve_opts *opts, size_t *bytes
 int fem_assemble(fem_handle *h, const double *u, const double *theta, double *residual, void *values,
                  int32_t values_dtype, int32_t values_layout, void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the residual of fem_assemble
+ * (residual [N] FP64 = R_int(u; theta) - F_ext, Dirichlet entries 0; u [N] FP64,
+ * theta [n_elems] FP64, device pointers owned by the caller) computed with the
+ * library's static device scratch array instead of a workspace, so the call allocates
+ * nothing.  Limit: n_elems * 8 * ndpn doubles of element terms must fit the 64 MiB
+ * array (up to 349,525 elements with 3 dofs per node, 1,048,576 with 1); larger meshes
+ * get FEM_ENOMEM before any work is enqueued.  Each GPU holds its own copy of the
+ * array until the process ends; every call on one GPU shares it, so calls that
+ * overlap on one GPU (different streams or threads) race.  Enqueue-only like
+ * fem_assemble: fem_check reports what the kernels found. */
+int fem_residual_noalloc(fem_handle *h, const double *u, const double *theta, double *residual, void *stream);
+
 /* Waits for `stream` and reports what the kernels of the enqueue-only calls
- * (fem_assemble) found since they cleared the status word: FEM_EMESH (det J <= 0 at a
+ * (fem_assemble, fem_residual_noalloc) found since they cleared the status word: FEM_EMESH (det J <= 0 at a
  * Gauss point), FEM_EINVERTED (det F <= 0), FEM_ENAN, or FEM_OK.  A reported condition
  * is cleared.  Blocks. */
 int fem_check(fem_handle *h, void *stream);

@@ -16,7 +16,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", str(ROOT / "include"), "-I", str(SRC),
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result",
           "-Wno-unknown-warning-option"]
-SOURCES = ["element.hip", "linalg.hip", "topopt.hip", "amg.hip", "setup.cpp", "solver.cpp", "abi.cpp"]
+SOURCES = ["element.hip", "linalg.hip", "topopt.hip", "amg.hip", "noalloc.hip", "setup.cpp", "solver.cpp", "abi.cpp"]
 
 
 def _compile(src: pathlib.Path, verbose: bool):

@@ -90,7 +90,7 @@ class MmaOpts(ctypes.Structure):
 
 # Names, in the order the header declares them (checked by the CPU test-suite).
 EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
-           "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_check", "fem_spmv",
+           "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_residual_noalloc", "fem_check", "fem_spmv",
            "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_history_copy", "fem_average_stress",
            "fem_amg_setup", "fem_amg_sizes", "fem_amg_export", "fem_amg_apply", "fem_param_vjp", "fem_element_volumes",
            "fem_filter_setup", "fem_filter_apply", "fem_vector_workspace_bytes", "fem_dot", "fem_mma_default_opts",
@@ -123,6 +123,7 @@ def lib():
         "fem_load_vector": (ctypes.c_int, [vp, vp, vp]),
         "fem_workspace_bytes": (ctypes.c_int, [vp, P(SolveOpts), P(sz)]),
         "fem_assemble": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]),
+        "fem_residual_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fem_check": (ctypes.c_int, [vp, vp]),
         "fem_spmv": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, dbl, dbl, vp]),
         "fem_apply_tangent": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -350,6 +351,17 @@ class Problem:
         if check:
             self.check()
         return r, vals
+
+    def residual_noalloc(self, u, theta=None, out: Optional[torch.Tensor] = None, check: bool = True):
+        """The FP64 residual through fem_residual_noalloc (static device scratch, no
+        workspace; meshes up to the library's limit)."""
+        u = self._f64(u, self.n_dofs)
+        theta = self.theta if theta is None else self._f64(theta, self.n_elems)
+        r = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device) if out is None else out
+        _check(lib().fem_residual_noalloc(self.handle, _ptr(u), _ptr(theta), _ptr(r), _stream()))
+        if check:
+            self.check()
+        return r
 
     def check(self):
         """Waits for the stream and raises what the enqueue-only kernels found (fem_check)."""
