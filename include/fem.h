@@ -194,6 +194,16 @@ int fem_default_opts(fem_solve_opts *opts);
  * mismatch), FEM_ERANGE (nnz >= 2^31), FEM_ENOMEM, FEM_EHIP. */
 int fem_build_pattern(const fem_mesh_desc *desc, fem_handle **out, int64_t *n_dofs, int64_t *nnz);
 
+/* The host half of fem_build_pattern, with no device and no handle: checks the mesh
+ * the same way, builds the node graph and the CSR pattern of the dof graph (Sec. 2.2,
+ * Alg. 1: the entries "Add K_e to K" touches) and the external load vector (Eq. (weak)
+ * with the nodal, traction and interpolated source terms).  Writes N and nnz; then,
+ * into caller HOST buffers that may each be NULL, row_ptr [N+1] int64, col_idx [nnz]
+ * int32 (ascending per row) and f_ext [N] FP64 (Dirichlet entries included).  A call
+ * with NULL arrays returns the sizes.  Synchronous; errors as fem_build_pattern. */
+int fem_pattern_host(const fem_mesh_desc *desc, int64_t *n_dofs, int64_t *nnz, int64_t *row_ptr, int32_t *col_idx,
+                     double *f_ext);
+
 /* Releases the handle and its device memory (NULL is accepted). */
 void fem_destroy(fem_handle *h);
 

@@ -1,4 +1,5 @@
 // C ABI of libfem: argument checks, handle lifetime, error translation.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -73,6 +74,44 @@ void check_workspace(const fem_handle *h, const fem_solve_opts *o, void *ws, siz
         throw fem::Error(FEM_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
 }
 
+// Host checks of a mesh description, before any device work.
+void validate_mesh(const fem_mesh_desc *d) {
+    require(d->n_nodes >= 0 && d->n_elems >= 0, "negative mesh size");
+    require(d->model == FEM_POISSON || d->model == FEM_LINEAR_ELASTIC || d->model == FEM_NEO_HOOKEAN ||
+                d->model == FEM_J2_PLASTIC,
+            "model");
+    require(d->ndpn == (d->model == FEM_POISSON ? 1 : 3), "ndpn must be 1 for FEM_POISSON and 3 otherwise");
+    require(d->pmap == FEM_THETA_IDENTITY || d->pmap == FEM_THETA_SIMP, "pmap");
+    require(d->n_nodes < (int64_t(1) << 31) / 3, "too many nodes for 32-bit dof indices");
+    require(d->n_nodes == 0 || d->coords != nullptr, "coords is NULL");
+    require(d->n_elems == 0 || d->conn != nullptr, "conn is NULL");
+    require(d->n_traction_faces >= 0 && (d->n_traction_faces == 0 || (d->traction_faces && d->traction)),
+            "traction faces");
+    if (d->model == FEM_LINEAR_ELASTIC) require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
+    if (d->model == FEM_NEO_HOOKEAN) require(d->bulk_ratio > 0.0, "bulk_ratio must be > 0");
+    if (d->model == FEM_J2_PLASTIC) {
+        require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
+        require(d->yield_stress > 0.0 && std::isfinite(d->yield_stress), "yield_stress must be > 0");
+    }
+    // every node must belong to an element (otherwise its row has no diagonal)
+    {
+        std::vector<uint8_t> used(d->n_nodes, 0);
+        for (int64_t i = 0; i < d->n_elems * 8; ++i) {
+            require(d->conn[i] >= 0 && d->conn[i] < d->n_nodes, "connectivity references a missing node");
+            used[d->conn[i]] = 1;
+        }
+        for (int64_t n = 0; n < d->n_nodes; ++n) require(used[n], "a node belongs to no element");
+        // A HEX8 element lists 8 distinct nodes: a collapsed element would send two of
+        // its node blocks to one matrix block, which the tangent gather adds once.
+        for (int64_t e = 0; e < d->n_elems; ++e) {
+            const int32_t *c = d->conn + 8 * e;
+            for (int a = 0; a < 8; ++a)
+                for (int b = a + 1; b < 8; ++b)
+                    require(c[a] != c[b], ("element " + std::to_string(e) + " lists a node twice").c_str());
+        }
+    }
+}
+
 }  // namespace
 
 int fem::run_guarded(const std::function<void()> &f) { return guarded(f); }
@@ -109,40 +148,7 @@ int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs,
     int rc = guarded([&] {
         require(d != nullptr && out != nullptr, "desc and out must be non-NULL");
         *out = nullptr;
-        require(d->n_nodes >= 0 && d->n_elems >= 0, "negative mesh size");
-        require(d->model == FEM_POISSON || d->model == FEM_LINEAR_ELASTIC || d->model == FEM_NEO_HOOKEAN ||
-                    d->model == FEM_J2_PLASTIC,
-                "model");
-        require(d->ndpn == (d->model == FEM_POISSON ? 1 : 3), "ndpn must be 1 for FEM_POISSON and 3 otherwise");
-        require(d->pmap == FEM_THETA_IDENTITY || d->pmap == FEM_THETA_SIMP, "pmap");
-        require(d->n_nodes < (int64_t(1) << 31) / 3, "too many nodes for 32-bit dof indices");
-        require(d->n_nodes == 0 || d->coords != nullptr, "coords is NULL");
-        require(d->n_elems == 0 || d->conn != nullptr, "conn is NULL");
-        require(d->n_traction_faces >= 0 && (d->n_traction_faces == 0 || (d->traction_faces && d->traction)),
-                "traction faces");
-        if (d->model == FEM_LINEAR_ELASTIC) require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
-        if (d->model == FEM_NEO_HOOKEAN) require(d->bulk_ratio > 0.0, "bulk_ratio must be > 0");
-        if (d->model == FEM_J2_PLASTIC) {
-            require(d->nu > -1.0 && d->nu < 0.5, "nu must be in (-1, 0.5)");
-            require(d->yield_stress > 0.0 && std::isfinite(d->yield_stress), "yield_stress must be > 0");
-        }
-        // every node must belong to an element (otherwise its row has no diagonal)
-        {
-            std::vector<uint8_t> used(d->n_nodes, 0);
-            for (int64_t i = 0; i < d->n_elems * 8; ++i) {
-                require(d->conn[i] >= 0 && d->conn[i] < d->n_nodes, "connectivity references a missing node");
-                used[d->conn[i]] = 1;
-            }
-            for (int64_t n = 0; n < d->n_nodes; ++n) require(used[n], "a node belongs to no element");
-            // A HEX8 element lists 8 distinct nodes: a collapsed element would send two of
-            // its node blocks to one matrix block, which the tangent gather adds once.
-            for (int64_t e = 0; e < d->n_elems; ++e) {
-                const int32_t *c = d->conn + 8 * e;
-                for (int a = 0; a < 8; ++a)
-                    for (int b = a + 1; b < 8; ++b)
-                        require(c[a] != c[b], ("element " + std::to_string(e) + " lists a node twice").c_str());
-            }
-        }
+        validate_mesh(d);
         h = new fem_handle();
         FEM_HIP(hipGetDevice(&h->device));
         FEM_HIP(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device));
@@ -176,6 +182,36 @@ int fem_build_pattern(const fem_mesh_desc *d, fem_handle **out, int64_t *n_dofs,
     });
     if (rc != FEM_OK && h) fem_destroy(h);
     return rc;
+}
+
+int fem_pattern_host(const fem_mesh_desc *d, int64_t *n_dofs, int64_t *nnz, int64_t *row_ptr, int32_t *col_idx,
+                     double *f_ext) {
+    return guarded([&] {
+        require(d != nullptr, "desc is NULL");
+        validate_mesh(d);
+        const int64_t N = d->n_nodes * d->ndpn;
+        std::vector<uint8_t> mask(N, 0);
+        if (d->dirichlet_mask)
+            for (int64_t i = 0; i < N; ++i) mask[i] = d->dirichlet_mask[i] ? 1 : 0;
+        const fem::HostGraph g = fem::host_graph(d, mask);
+        if (n_dofs) *n_dofs = g.N;
+        if (nnz) *nnz = g.nnz;
+        if (row_ptr) std::copy(g.row_ptr.begin(), g.row_ptr.end(), row_ptr);
+        if (col_idx) {
+            // the nd rows of node n list the node's neighbour blocks, component-interleaved
+            const int nd = g.nd;
+            for (int64_t n = 0; n < g.Nn; ++n)
+                for (int c = 0; c < nd; ++c) {
+                    int64_t pos = g.row_ptr[nd * n + c];
+                    for (int64_t k = g.node_ptr[n]; k < g.node_ptr[n + 1]; ++k)
+                        for (int q = 0; q < nd; ++q) col_idx[pos++] = int32_t(int64_t(nd) * g.node_nb[k] + q);
+                }
+        }
+        if (f_ext) {
+            const std::vector<double> F = fem::host_load_vector(d);
+            std::copy(F.begin(), F.end(), f_ext);
+        }
+    });
 }
 
 void fem_destroy(fem_handle *h) {

@@ -167,6 +167,18 @@ struct fem_handle {
 namespace fem {
 
 // ------------------------------------------------------------------ setup (host)
+// The sparsity structure built on the host (host_graph, no device work); build_graph
+// uploads it into the handle's Graph (same array meanings).
+struct HostGraph {
+    int64_t Nn = 0, Ne = 0, N = 0, nnz = 0, nnzb = 0, nnzb_up = 0;
+    int nd = 1, max_deg = 0;
+    std::vector<int64_t> ne_ptr, node_ptr, blk_ptr, row_ptr, up_base;
+    std::vector<int32_t> kpos, node_nb, blk_row, mirror, bdiag, bslot, blk_src, lo_val;
+    std::vector<int16_t> dnb;  // empty when some neighbour offset needs more than 16 bits
+    std::vector<uint8_t> tgt, nb_bits;
+};
+HostGraph host_graph(const fem_mesh_desc *d, const std::vector<uint8_t> &mask);
+std::vector<double> host_load_vector(const fem_mesh_desc *d);
 void build_graph(fem_handle *h, const fem_mesh_desc *d);
 void build_load_vector(fem_handle *h, const fem_mesh_desc *d);
 void *dev_alloc(fem_handle *h, size_t bytes);

@@ -43,8 +43,8 @@ static void parallel_for(int64_t n, F fn) {
     for (auto &t : th) t.join();
 }
 
-void build_graph(fem_handle *h, const fem_mesh_desc *d) {
-    Graph &g = h->g;
+HostGraph host_graph(const fem_mesh_desc *d, const std::vector<uint8_t> &mask) {
+    HostGraph g;
     const int64_t Nn = d->n_nodes, Ne = d->n_elems;
     const int nd = d->ndpn;
     const int32_t *conn = d->conn;
@@ -57,7 +57,8 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
         if (conn[i] < 0 || conn[i] >= Nn) throw Error(FEM_EINVAL, "element connectivity references a missing node");
 
     // node -> (element, local node) incidence, element ascending within a node
-    std::vector<int64_t> ne_ptr(Nn + 1, 0);
+    std::vector<int64_t> &ne_ptr = g.ne_ptr;
+    ne_ptr.assign(Nn + 1, 0);
     for (int64_t i = 0; i < Ne * 8; ++i) ne_ptr[conn[i] + 1]++;
     for (int64_t n = 0; n < Nn; ++n) ne_ptr[n + 1] += ne_ptr[n];
     std::vector<int32_t> ne_list(Ne * 8);
@@ -69,11 +70,13 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     // Element outputs are written in this node-major incidence order: (e, a) goes to
     // slot kpos[e*8 + a], so the contributions of node n are the contiguous slots
     // ne_ptr[n] .. ne_ptr[n+1] and the gathers read them as one run.
-    std::vector<int32_t> kpos(Ne * 8);
+    std::vector<int32_t> &kpos = g.kpos;
+    kpos.resize(Ne * 8);
     for (int64_t s = 0; s < Ne * 8; ++s) kpos[ne_list[s]] = int32_t(s);
 
     // neighbour sets: nodes sharing an element, ascending, unique
-    std::vector<int64_t> node_ptr(Nn + 1, 0);
+    std::vector<int64_t> &node_ptr = g.node_ptr;
+    node_ptr.assign(Nn + 1, 0);
     auto neighbours = [&](int64_t n, std::vector<int32_t> &buf) {
         buf.clear();
         for (int64_t s = ne_ptr[n]; s < ne_ptr[n + 1]; ++s) {
@@ -95,8 +98,9 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     g.nnzb = nnzb;
     g.nnz = nnzb * nd * nd;
     if (g.nnz >= (int64_t(1) << 31)) throw Error(FEM_ERANGE, "nnz >= 2^31 does not fit 32-bit CSR positions");
-    std::vector<int32_t> node_nb(nnzb);
-    std::vector<int32_t> blk_row(nnzb);
+    std::vector<int32_t> &node_nb = g.node_nb, &blk_row = g.blk_row;
+    node_nb.resize(nnzb);
+    blk_row.resize(nnzb);
     parallel_for(Nn, [&](int64_t b, int64_t e) {
         std::vector<int32_t> buf;
         for (int64_t n = b; n < e; ++n) {
@@ -110,7 +114,9 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
         auto it = std::lower_bound(first, last, m);
         return (it != last && *it == m) ? int64_t(it - node_nb.begin()) : -1;
     };
-    std::vector<int32_t> mirror(nnzb), bdiag(Nn);
+    std::vector<int32_t> &mirror = g.mirror, &bdiag = g.bdiag;
+    mirror.resize(nnzb);
+    bdiag.resize(Nn);
     parallel_for(Nn, [&](int64_t b, int64_t e) {
         for (int64_t n = b; n < e; ++n) {
             for (int64_t k = node_ptr[n]; k < node_ptr[n + 1]; ++k) mirror[k] = int32_t(find_block(node_nb[k], int32_t(n)));
@@ -119,7 +125,8 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     });
 
     // element-pair -> block slot, and its inverse (contributions per block)
-    std::vector<int32_t> bslot(Ne * 64);
+    std::vector<int32_t> &bslot = g.bslot;
+    bslot.resize(Ne * 64);
     parallel_for(Ne, [&](int64_t b, int64_t e_end) {
         for (int64_t e = b; e < e_end; ++e)
             for (int a = 0; a < 8; ++a)
@@ -130,7 +137,7 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     int64_t max_deg = 0;
     for (int64_t n = 0; n < Nn; ++n) max_deg = std::max(max_deg, node_ptr[n + 1] - node_ptr[n]);
     g.max_deg = int(max_deg);
-    std::vector<uint8_t> tgt;
+    std::vector<uint8_t> &tgt = g.tgt;
     if (max_deg <= 255) {
         tgt.resize(Ne * 64);
         parallel_for(Ne, [&](int64_t b, int64_t e_end) {
@@ -141,10 +148,12 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
                 }
         });
     }
-    std::vector<int64_t> blk_ptr(nnzb + 1, 0);
+    std::vector<int64_t> &blk_ptr = g.blk_ptr;
+    blk_ptr.assign(nnzb + 1, 0);
     for (int64_t i = 0; i < Ne * 64; ++i) blk_ptr[bslot[i] + 1]++;
     for (int64_t k = 0; k < nnzb; ++k) blk_ptr[k + 1] += blk_ptr[k];
-    std::vector<int32_t> blk_src(Ne * 64);
+    std::vector<int32_t> &blk_src = g.blk_src;
+    blk_src.resize(Ne * 64);
     {
         std::vector<int64_t> fill(blk_ptr.begin(), blk_ptr.end() - 1);
         // contribution (e, a, b) lives in element row block kpos[e*8+a], column block b
@@ -152,7 +161,8 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
     }
 
     // scalar CSR row starts: the nd rows of node n share the node's block list
-    std::vector<int64_t> row_ptr(g.N + 1);
+    std::vector<int64_t> &row_ptr = g.row_ptr;
+    row_ptr.resize(g.N + 1);
     for (int64_t n = 0; n < Nn; ++n) {
         int64_t deg = node_ptr[n + 1] - node_ptr[n];
         for (int c = 0; c < nd; ++c) row_ptr[nd * n + c] = int64_t(nd) * nd * node_ptr[n] + int64_t(c) * nd * deg;
@@ -161,9 +171,11 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
 
     // symmetric block layout: the upper blocks of node n are the tail of its sorted
     // neighbour list, starting at the diagonal block
-    std::vector<int64_t> up_base(Nn + 1, 0);
+    std::vector<int64_t> &up_base = g.up_base;
+    up_base.assign(Nn + 1, 0);
     for (int64_t n = 0; n < Nn; ++n) up_base[n + 1] = up_base[n] + (node_ptr[n + 1] - bdiag[n]);
-    std::vector<int32_t> lo_val(nnzb, -1);
+    std::vector<int32_t> &lo_val = g.lo_val;
+    lo_val.assign(nnzb, -1);
     parallel_for(Nn, [&](int64_t b, int64_t e) {
         for (int64_t n = b; n < e; ++n)
             for (int64_t k = node_ptr[n]; k < bdiag[n]; ++k) {  // lower blocks (n, m), m < n
@@ -172,42 +184,55 @@ void build_graph(fem_handle *h, const fem_mesh_desc *d) {
             }
     });
     g.nnzb_up = up_base[Nn];
-    g.up_base = upload(h, up_base);
-    g.lo_val = upload(h, lo_val);
-    g.node_ptr = upload(h, node_ptr);
-    g.node_nb = upload(h, node_nb);
     {  // 16-bit neighbour offsets for the SpMV when the numbering keeps neighbours close
         bool fits = true;
         std::vector<int16_t> dnb(nnzb);
         for (int64_t n = 0; n < Nn && fits; ++n)
             for (int64_t k = node_ptr[n]; k < node_ptr[n + 1]; ++k) {
-                const int64_t d = int64_t(node_nb[k]) - n;
-                if (d < -32768 || d > 32767) {
+                const int64_t dd = int64_t(node_nb[k]) - n;
+                if (dd < -32768 || dd > 32767) {
                     fits = false;
                     break;
                 }
-                dnb[k] = int16_t(d);
+                dnb[k] = int16_t(dd);
             }
-        if (fits) g.node_dnb = upload(h, dnb);
+        if (fits) g.dnb = std::move(dnb);
     }
-    {  // Dirichlet bits of every block's column node (one load per neighbour in the gather)
-        std::vector<uint8_t> bits(nnzb, 0);
-        const std::vector<uint8_t> &mk = h->m.host_mask;
-        if (!mk.empty())
-            for (int64_t k = 0; k < nnzb; ++k)
-                for (int c = 0; c < nd; ++c) bits[k] |= uint8_t((mk[int64_t(nd) * node_nb[k] + c] != 0) << c);
-        g.nb_bits = upload(h, bits);
-    }
-    g.blk_row = upload(h, blk_row);
-    g.mirror = upload(h, mirror);
-    g.bdiag = upload(h, bdiag);
-    g.blk_ptr = upload(h, blk_ptr);
-    g.blk_src = upload(h, blk_src);
-    g.ne_ptr = upload(h, ne_ptr);
-    g.kpos = upload(h, kpos);
-    if (!tgt.empty()) g.tgt = upload(h, tgt);
-    g.bslot = upload(h, bslot);
-    g.row_ptr = upload(h, row_ptr);
+    // Dirichlet bits of every block's column node (one load per neighbour in the gather)
+    g.nb_bits.assign(nnzb, 0);
+    if (!mask.empty())
+        for (int64_t k = 0; k < nnzb; ++k)
+            for (int c = 0; c < nd; ++c) g.nb_bits[k] |= uint8_t((mask[int64_t(nd) * node_nb[k] + c] != 0) << c);
+    return g;
+}
+
+void build_graph(fem_handle *h, const fem_mesh_desc *d) {
+    HostGraph hg = host_graph(d, h->m.host_mask);
+    Graph &g = h->g;
+    g.Nn = hg.Nn;
+    g.Ne = hg.Ne;
+    g.nd = hg.nd;
+    g.N = hg.N;
+    g.nnz = hg.nnz;
+    g.nnzb = hg.nnzb;
+    g.nnzb_up = hg.nnzb_up;
+    g.max_deg = hg.max_deg;
+    g.up_base = upload(h, hg.up_base);
+    g.lo_val = upload(h, hg.lo_val);
+    g.node_ptr = upload(h, hg.node_ptr);
+    g.node_nb = upload(h, hg.node_nb);
+    if (!hg.dnb.empty()) g.node_dnb = upload(h, hg.dnb);
+    g.nb_bits = upload(h, hg.nb_bits);
+    g.blk_row = upload(h, hg.blk_row);
+    g.mirror = upload(h, hg.mirror);
+    g.bdiag = upload(h, hg.bdiag);
+    g.blk_ptr = upload(h, hg.blk_ptr);
+    g.blk_src = upload(h, hg.blk_src);
+    g.ne_ptr = upload(h, hg.ne_ptr);
+    g.kpos = upload(h, hg.kpos);
+    if (!hg.tgt.empty()) g.tgt = upload(h, hg.tgt);
+    g.bslot = upload(h, hg.bslot);
+    g.row_ptr = upload(h, hg.row_ptr);
 }
 
 // ------------------------------------------------------------------ external loads
@@ -224,7 +249,7 @@ static void hex8_shape(const double s[3], double N[8], double dN[8][3]) {
     }
 }
 
-void build_load_vector(fem_handle *h, const fem_mesh_desc *d) {
+std::vector<double> host_load_vector(const fem_mesh_desc *d) {
     const int64_t Nn = d->n_nodes, Ne = d->n_elems, N = Nn * d->ndpn;
     const int nd = d->ndpn;
     std::vector<double> F(N, 0.0);
@@ -281,6 +306,12 @@ void build_load_vector(fem_handle *h, const fem_mesh_desc *d) {
             }
         }
     }
+    return F;
+}
+
+void build_load_vector(fem_handle *h, const fem_mesh_desc *d) {
+    const int64_t N = d->n_nodes * d->ndpn;
+    std::vector<double> F = host_load_vector(d);
     double nrm = 0.0;
     for (int64_t i = 0; i < N; ++i)
         if (!(d->dirichlet_mask && d->dirichlet_mask[i])) nrm += F[i] * F[i];

@@ -8,6 +8,7 @@ is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import os
 import pathlib
 from typing import Optional
 
@@ -16,7 +17,7 @@ import torch
 
 from . import inputs
 
-_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libfem.so"
+_LIB_PATH = pathlib.Path(os.environ.get("FEM_LIBRARY") or pathlib.Path(__file__).resolve().parent / "libfem.so")
 
 FEM_OK = 0
 ERRORS = {-1: "FEM_EINVAL", -2: "FEM_ERANGE", -3: "FEM_EHIP", -4: "FEM_EMESH", -5: "FEM_EINVERTED",
@@ -89,7 +90,7 @@ class MmaOpts(ctypes.Structure):
 
 
 # Names, in the order the header declares them (checked by the CPU test-suite).
-EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_destroy", "fem_pattern_export",
+EXPORTS = ["fem_last_error", "fem_default_opts", "fem_build_pattern", "fem_pattern_host", "fem_destroy", "fem_pattern_export",
            "fem_values_count", "fem_load_vector", "fem_workspace_bytes", "fem_assemble", "fem_residual_noalloc", "fem_check", "fem_spmv",
            "fem_apply_tangent", "fem_newton_solve", "fem_adjoint_vjp", "fem_history_copy", "fem_average_stress",
            "fem_amg_setup", "fem_amg_sizes", "fem_amg_export", "fem_amg_apply", "fem_param_vjp", "fem_element_volumes",
@@ -117,6 +118,7 @@ def lib():
         "fem_last_error": (ctypes.c_char_p, []),
         "fem_default_opts": (ctypes.c_int, [P(SolveOpts)]),
         "fem_build_pattern": (ctypes.c_int, [P(MeshDesc), P(vp), P(i64), P(i64)]),
+        "fem_pattern_host": (ctypes.c_int, [P(MeshDesc), P(i64), P(i64), vp, vp, vp]),
         "fem_destroy": (None, [vp]),
         "fem_pattern_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "fem_values_count": (ctypes.c_int, [vp, i32, P(i64)]),
@@ -244,6 +246,38 @@ def _host(a, dt):
     return None if a is None else np.ascontiguousarray(a, dtype=dt)
 
 
+def _keep_arrays(prob: inputs.Problem) -> dict:
+    return dict(coords=_host(prob.coords, np.float64), conn=_host(prob.conn, np.int32),
+                mask=_host(prob.dirichlet_mask, np.uint8), f=_host(prob.f_nodal, np.float64),
+                src=_host(prob.source_nodal, np.float64), faces=_host(prob.traction_faces, np.int32),
+                trac=_host(prob.traction, np.float64))
+
+
+def _mesh_desc(prob: inputs.Problem, k: dict) -> MeshDesc:
+    """fem_mesh_desc over the host arrays in k (which must outlive its use)."""
+    def p(a):
+        return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    return MeshDesc(prob.n_nodes, prob.n_elems, prob.ndpn, prob.model, prob.pmap, 0, prob.nu, prob.bulk_ratio,
+                    prob.simp_p, prob.simp_emin, prob.simp_e0, p(k["coords"]), p(k["conn"]), p(k["mask"]),
+                    p(k["f"]), p(k["src"]), 0 if k["faces"] is None else k["faces"].shape[0], p(k["faces"]),
+                    p(k["trac"]), float(getattr(prob, "yield_stress", 0.0)))
+
+
+def pattern_host(prob: inputs.Problem):
+    """(row_ptr, col_idx, f_ext) built on the host by fem_pattern_host (no GPU)."""
+    k = _keep_arrays(prob)
+    d = _mesh_desc(prob, k)
+    n, nnz = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fem_pattern_host(ctypes.byref(d), ctypes.byref(n), ctypes.byref(nnz), None, None, None))
+    row_ptr = np.empty(n.value + 1, dtype=np.int64)
+    col_idx = np.empty(max(nnz.value, 1), dtype=np.int32)
+    f = np.empty(max(n.value, 1), dtype=np.float64)
+    _check(lib().fem_pattern_host(ctypes.byref(d), ctypes.byref(n), ctypes.byref(nnz),
+                                  row_ptr.ctypes.data_as(ctypes.c_void_p), col_idx.ctypes.data_as(ctypes.c_void_p),
+                                  f.ctypes.data_as(ctypes.c_void_p)))
+    return row_ptr, col_idx[:nnz.value], f[:n.value]
+
+
 class Problem:
     """A mesh + material + loads bound to a libfem handle on the current GPU."""
 
@@ -251,18 +285,8 @@ class Problem:
         L = lib()
         self.spec = prob
         self.device = torch.device(device)
-        self._keep = dict(coords=_host(prob.coords, np.float64), conn=_host(prob.conn, np.int32),
-                          mask=_host(prob.dirichlet_mask, np.uint8), f=_host(prob.f_nodal, np.float64),
-                          src=_host(prob.source_nodal, np.float64),
-                          faces=_host(prob.traction_faces, np.int32), trac=_host(prob.traction, np.float64))
-        k = self._keep
-
-        def p(a):
-            return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
-        d = MeshDesc(prob.n_nodes, prob.n_elems, prob.ndpn, prob.model, prob.pmap, 0, prob.nu, prob.bulk_ratio,
-                     prob.simp_p, prob.simp_emin, prob.simp_e0, p(k["coords"]), p(k["conn"]), p(k["mask"]),
-                     p(k["f"]), p(k["src"]), 0 if k["faces"] is None else k["faces"].shape[0], p(k["faces"]),
-                     p(k["trac"]), float(getattr(prob, "yield_stress", 0.0)))
+        self._keep = _keep_arrays(prob)
+        d = _mesh_desc(prob, self._keep)
         h = ctypes.c_void_p()
         n, nnz = ctypes.c_int64(), ctypes.c_int64()
         with torch.cuda.device(self.device):
