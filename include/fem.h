@@ -152,6 +152,13 @@ typedef struct {
                                and the remaining increment is halved, at most this many times per
                                load step */
     int32_t reserved_opts;
+    double refine_rtol;     /* FEM_PREC_MIXED Newton corrections (0 = off): the correction K du = b is
+                               solved to ||b - K du|| <= krylov_rtol ||b|| measured in FP64 with the
+                               matrix-free tangent, by FP32 Krylov sweeps that each reduce the FP64
+                               residual by at most this factor (each restarts from the FP64 residual;
+                               at most adjoint_max_refine sweeps).  Off: one FP32 solve to krylov_rtol on
+                               its recursive residual.  The mixed adjoint's sweeps likewise ask for at
+                               most this reduction each (instead of krylov_rtol). */
 } fem_solve_opts;
 
 #define FEM_MAX_HIST 64

@@ -51,6 +51,7 @@ void validate_opts(const fem_solve_opts *o) {
     require(o->adjoint_max_refine >= 1, "opts.adjoint_max_refine must be >= 1");
     require(o->newton_fixed_its >= 0, "opts.newton_fixed_its must be >= 0");
     require(o->max_bisections >= 0 && o->max_bisections <= 30, "opts.max_bisections must be in [0, 30]");
+    require(o->refine_rtol >= 0.0 && o->refine_rtol < 1.0, "opts.refine_rtol must be in [0, 1)");
     require(o->precond == FEM_PRECOND_JACOBI || o->precond == FEM_PRECOND_BLOCK_JACOBI ||
                 o->precond == FEM_PRECOND_AMG,
             "opts.precond");

@@ -60,6 +60,10 @@ struct KrylovScalars {
     // CG: rho of iteration k lives in rho_pp[k & 1], so a kernel that publishes the
     // next rho never overwrites the value its other blocks are still reading
     double rho_pp[2];
+    // BiCGSTAB (fused form): the scalars of iteration k in slot k & 1 -- alpha and omega,
+    // |rhat|^2 and the smallest |r|^2 so far -- written by one kernel of iteration k and
+    // read by kernels of iteration k + 1, never by blocks of the kernel writing them
+    double alpha_pp[2], omega_pp[2], rh2_pp[2], rmin2_pp[2];
 };
 constexpr size_t kScalarsHostBytes = sizeof(KrylovScalars);
 
@@ -238,8 +242,13 @@ struct KrylovVecs {
 
 template <typename T>
 void kry_bicg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
+// BiCGSTAB iteration number `it` (0-based within this solve).  With the point Jacobi
+// preconditioner the scalar updates are folded into the vector kernels, and
+// kry_bicg_check brings the convergence flag up to date after iteration it - 1.
 template <typename T>
-void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev);
+void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev);
+template <typename T>
+void kry_bicg_check(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s);
 template <typename T>
 void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double rtol, hipStream_t s);
 // Two-level preconditioned CG (amg.hip): init (z = M b) and iteration `it`.

@@ -471,41 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_fin_omega(int G, const double *__r
     if (threadIdx.x == 0) sc->omega = (tot[1] > 0.0 && isfinite(tot[1])) ? tot[0] / tot[1] : 0.0;
 }
 
-// BiCGSTAB: beta = (rho/rho_old)(alpha/omega); p = r + beta (p - omega v); ph = Dinv p.
-// On a restart iteration the shadow residual and the direction restart from r.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bicg_p(int64_t N, const T *__restrict__ r, T *__restrict__ p,
-                                                     const T *__restrict__ v, T *__restrict__ ph,
-                                                     T *__restrict__ rh, const T *__restrict__ dinv,
-                                                     const KrylovScalars *sc) {
-    if (stopped(sc)) return;
-    const bool restart = sc->restart_at == sc->its;
-    const double beta = (sc->its == 0 || restart) ? 0.0 : (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
-    const T bt = T(beta), om = T(sc->omega);
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
-        T ri = r[i];
-        T pi = restart ? ri : ri + bt * (p[i] - om * v[i]);
-        p[i] = pi;
-        ph[i] = dinv[i] * pi;
-        if (restart) rh[i] = ri;
-    }
-}
-
-// BiCGSTAB: s = r - alpha v; sh = Dinv s
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t N, const T *__restrict__ r, const T *__restrict__ v,
-                                                     T *__restrict__ s, T *__restrict__ sh,
-                                                     const T *__restrict__ dinv, const KrylovScalars *sc) {
-    if (stopped(sc)) return;
-    const T al = T(sc->alpha);
-    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads) {
-        T si = r[i] - al * v[i];
-        s[i] = si;
-        sh[i] = dinv[i] * si;
-    }
-}
-
-// BiCGSTAB: x += alpha ph + omega sh; r = s - omega t; rho_new = (rh, r); |r|^2
+// BiCGSTAB (block Jacobi form): x += alpha ph + omega sh; r = s - omega t; rho_new = (rh, r); |r|^2
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t N, T *__restrict__ x, T *__restrict__ r,
                                                       const T *__restrict__ rh, const T *__restrict__ ph,
@@ -652,6 +618,191 @@ __global__ __launch_bounds__(kThreads) void k_cg_p_fused(int64_t N, const T *__r
         V::st_nt(p, i, V::ld(z, i) + bt * V::ld(p, i));
     if (blockIdx.x == 0)
         for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) p[i] = z[i] + bt * p[i];
+}
+
+// ------------------------------------------------------------------ fused BiCGSTAB
+// The point-Jacobi BiCGSTAB with its scalar updates folded into the vector kernels
+// (every block sums the previous kernel's partials in block order, so all blocks agree
+// bit for bit and no one-block finalize kernel is launched).  Iteration i:
+//   p-kernel:  rho_i, |r_i|^2 from the (rhat, r), (r, r) partials of iteration i - 1;
+//              convergence, divergence and restart tests; p = r + beta (p - omega v)
+//              (or p = r, rhat = r on a restart); ph = Dinv p
+//   SpMV:      v = K ph with the (rhat, v) partials
+//   s-kernel:  alpha = rho_i / (rhat, v); s = r - alpha v; sh = Dinv s
+//   SpMV:      t = K sh with the (t, s), (t, t) partials
+//   xr-kernel: omega = (t, s) / (t, t); x += alpha ph + omega sh; r = s - omega t, and
+//              the (rhat, r), (r, r) partials for iteration i + 1.
+// The scalars of iteration i go to slot i & 1 (see KrylovScalars).
+
+struct BicgStart {
+    double rho, r2, rh2, rmin2;
+    bool nan, conv, div, restart;
+};
+
+// Tests at the start of iteration i (>= 1) from the partial sums tot = ((rhat, r), |r|^2)
+// of iteration i - 1: the same rules as the unfused finalize.
+__device__ BicgStart bicg_start(const double tot[2], const KrylovScalars *sc, int i) {
+    const int q = (i - 1) & 1;
+    BicgStart b;
+    b.r2 = tot[1];
+    b.nan = !isfinite(tot[0]) || !isfinite(tot[1]);
+    b.conv = !b.nan && tot[1] <= sc->tol2;
+    b.div = !b.nan && !b.conv && tot[1] > 1e12 * sc->bnorm2;
+    const double rh2 = sc->rh2_pp[q], rmin2 = sc->rmin2_pp[q];
+    // (rhat, r) lost its size relative to |rhat||r|, omega vanished, or the residual
+    // grew 1000x above its best value: restart from the current r
+    b.restart = !(fabs(tot[0]) > 1e-9 * sqrt(rh2 * tot[1])) || sc->omega_pp[q] == 0.0 || tot[1] > 1e6 * rmin2;
+    b.rho = b.restart ? tot[1] : tot[0];
+    b.rh2 = b.restart ? tot[1] : rh2;
+    b.rmin2 = fmin(rmin2, tot[1]);
+    return b;
+}
+
+__device__ __forceinline__ void bicg_publish_start(const BicgStart &b, KrylovScalars *sc, int i) {
+    sc->its = i;
+    sc->rnorm2 = b.r2;
+    if (b.nan) sc->breakdown = 2;
+    else if (b.conv) sc->converged = 1;
+    else if (b.div) sc->breakdown = 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_p_fused(int64_t N, int it, const T *__restrict__ r,
+                                                           T *__restrict__ p, const T *__restrict__ v,
+                                                           T *__restrict__ ph, T *__restrict__ rh,
+                                                           const T *__restrict__ dinv,
+                                                           const double *__restrict__ xr_partials, int xr_count,
+                                                           KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    bool restart = false;
+    double beta = 0.0, omega = 0.0;
+    if (it > 0) {
+        double tot[2];
+        sum_partials<2>(xr_partials, xr_count, tot);
+        const BicgStart b = bicg_start(tot, sc, it);
+        const int q = (it - 1) & 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            bicg_publish_start(b, sc, it);
+            sc->rho_old = sc->rho_pp[q];
+            sc->rho = b.rho;
+            sc->rho_pp[it & 1] = b.rho;
+            sc->rh2_pp[it & 1] = b.rh2;
+            sc->rmin2_pp[it & 1] = b.rmin2;
+            if (b.restart) sc->restart_at = it;
+        }
+        if (b.nan || b.conv || b.div) return;
+        restart = b.restart;
+        omega = sc->omega_pp[q];
+        if (!restart) beta = (b.rho / sc->rho_pp[q]) * (sc->alpha_pp[q] / omega);
+    }
+    const T bt = T(beta), om = T(omega);
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t NV = N / W;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads) {
+        const typename V::type rv = V::ld(r, i);
+        const typename V::type pv = restart ? rv : rv + bt * (V::ld(p, i) - om * V::ld(v, i));
+        V::st(p, i, pv);
+        V::st(ph, i, V::ld(dinv, i) * pv);
+        if (restart) V::st(rh, i, rv);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) {
+            const T ri = r[i];
+            const T pi = restart ? ri : ri + bt * (p[i] - om * v[i]);
+            p[i] = pi;
+            ph[i] = dinv[i] * pi;
+            if (restart) rh[i] = ri;
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_s_fused(int64_t N, int it, const T *__restrict__ r,
+                                                           const T *__restrict__ v, T *__restrict__ s,
+                                                           T *__restrict__ sh, const T *__restrict__ dinv,
+                                                           const double *__restrict__ sp_partials, int sp_count,
+                                                           KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    double tot[1];
+    sum_partials<1>(sp_partials, sp_count, tot);
+    if (!(tot[0] != 0.0) || !isfinite(tot[0])) {  // (rhat, v) vanished
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->breakdown = 1;
+        return;
+    }
+    const double alpha = sc->rho_pp[it & 1] / tot[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->alpha_pp[it & 1] = alpha;
+        sc->alpha = alpha;
+    }
+    const T al = T(alpha);
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t NV = N / W;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads) {
+        const typename V::type sv = V::ld(r, i) - al * V::ld(v, i);
+        V::st(s, i, sv);
+        V::st(sh, i, V::ld(dinv, i) * sv);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) {
+            const T si = r[i] - al * v[i];
+            s[i] = si;
+            sh[i] = dinv[i] * si;
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_xr_fused(int64_t N, int it, T *__restrict__ x, T *__restrict__ r,
+                                                            const T *__restrict__ rh, const T *__restrict__ ph,
+                                                            const T *__restrict__ s, const T *__restrict__ sh,
+                                                            const T *__restrict__ t,
+                                                            const double *__restrict__ sp_partials, int sp_count,
+                                                            double *xr_partials, KrylovScalars *sc) {
+    if (stopped(sc)) return;
+    double tot[2];
+    sum_partials<2>(sp_partials, sp_count, tot);
+    const double omega = (tot[1] > 0.0 && isfinite(tot[1])) ? tot[0] / tot[1] : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->omega_pp[it & 1] = omega;
+        sc->omega = omega;
+    }
+    const T al = T(sc->alpha_pp[it & 1]), om = T(omega);
+    double d0 = 0.0, d1 = 0.0;
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t NV = N / W;
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads) {
+        V::st(x, i, V::ld(x, i) + al * V::ld(ph, i) + om * V::ld(sh, i));
+        const typename V::type rv = V::ld(s, i) - om * V::ld(t, i);
+        const typename V::type hv = V::ld(rh, i);
+        V::st(r, i, rv);
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            d0 += double(hv[c]) * double(rv[c]);
+            d1 += double(rv[c]) * double(rv[c]);
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) {
+            x[i] += al * ph[i] + om * sh[i];
+            const T ri = s[i] - om * t[i];
+            r[i] = ri;
+            d0 += double(rh[i]) * double(ri);
+            d1 += double(ri) * double(ri);
+        }
+    double vv[2] = {d0, d1};
+    block_store_partials<2>(vv, xr_partials);
+}
+
+// Convergence, divergence and NaN flags after iteration it - 1 (one block; the next
+// p-kernel repeats the same tests and also takes the restart decision).
+__global__ __launch_bounds__(kThreads) void k_bicg_check(int it, const double *__restrict__ xr_partials,
+                                                         int xr_count, KrylovScalars *sc) {
+    if (stopped(sc) || it == 0) return;
+    double tot[2];
+    sum_partials<2>(xr_partials, xr_count, tot);
+    const BicgStart b = bicg_start(tot, sc, it);
+    if (threadIdx.x == 0) bicg_publish_start(b, sc, it);
 }
 
 // ------------------------------------------------------------------ block Jacobi variants
@@ -834,6 +985,10 @@ __global__ __launch_bounds__(kThreads) void k_fin_init(int G, const double *__re
         sc->rh2 = tot[1];
         sc->rmin2 = tot[1];
         sc->restart_at = -1;
+        sc->alpha_pp[0] = sc->alpha_pp[1] = 1.0;
+        sc->omega_pp[0] = sc->omega_pp[1] = 1.0;
+        sc->rh2_pp[0] = sc->rh2_pp[1] = tot[1];
+        sc->rmin2_pp[0] = sc->rmin2_pp[1] = tot[1];
         sc->breakdown = isfinite(tot[1]) ? 0 : 2;
         sc->converged = (tot[1] == 0.0) ? 1 : 0;
     }
@@ -1152,25 +1307,48 @@ void launch_spmv_sc(const fem_handle *h, const T *values, const T *x, T *y, T al
 }
 
 template <typename T>
-void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, hipStream_t s, hipEvent_t *ev) {
+void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s, hipEvent_t *ev) {
     const int64_t N = h->g.N;
-    dim3 grid(krylov_grid(h)), blk(kThreads);
     const T *A = k.A;
     const int64_t Nn = h->g.Nn;
-    if (!k.bj) hipLaunchKernelGGL((k_bicg_p<T>), grid, blk, 0, s, N, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
-    else if (h->g.nd == 1) hipLaunchKernelGGL((k_bicg_p_bj<1, T>), grid, blk, 0, s, Nn, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
+    if (!k.bj) {
+        dim3 grid(krylov_vec_grid(h)), blk(kThreads);
+        hipLaunchKernelGGL((k_bicg_p_fused<T>), grid, blk, 0, s, N, it, k.r, k.p, k.v, k.ph, k.rh, k.dinv,
+                           k.partials2, int(grid.x), k.sc);
+        if (ev) FEM_HIP(hipEventRecord(ev[0], s));
+        int G = kry_spmv<T, 1>(h, k.ph, k.v, k.rh, k, 0, A, s, false);
+        if (ev) FEM_HIP(hipEventRecord(ev[1], s));
+        hipLaunchKernelGGL((k_bicg_s_fused<T>), grid, blk, 0, s, N, it, k.r, k.v, k.s, k.sh, k.dinv, k.partials, G,
+                           k.sc);
+        if (ev) FEM_HIP(hipEventRecord(ev[2], s));
+        G = kry_spmv<T, 2>(h, k.sh, k.t, k.s, k, 0, A, s, false);
+        if (ev) FEM_HIP(hipEventRecord(ev[3], s));
+        hipLaunchKernelGGL((k_bicg_xr_fused<T>), grid, blk, 0, s, N, it, k.x, k.r, k.rh, k.ph, k.s, k.sh, k.t,
+                           k.partials, G, k.partials2, k.sc);
+        FEM_HIP(hipGetLastError());
+        return;
+    }
+    // block Jacobi: separate vector kernels with one-block finalizes
+    dim3 grid(krylov_grid(h)), blk(kThreads);
+    if (h->g.nd == 1) hipLaunchKernelGGL((k_bicg_p_bj<1, T>), grid, blk, 0, s, Nn, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
     else hipLaunchKernelGGL((k_bicg_p_bj<3, T>), grid, blk, 0, s, Nn, k.r, k.p, k.v, k.ph, k.rh, k.dinv, k.sc);
     if (ev) FEM_HIP(hipEventRecord(ev[0], s));
     kry_spmv<T, 1>(h, k.ph, k.v, k.rh, k, 0, A, s);
     if (ev) FEM_HIP(hipEventRecord(ev[1], s));
-    if (!k.bj) hipLaunchKernelGGL((k_bicg_s<T>), grid, blk, 0, s, N, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
-    else if (h->g.nd == 1) hipLaunchKernelGGL((k_bicg_s_bj<1, T>), grid, blk, 0, s, Nn, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
+    if (h->g.nd == 1) hipLaunchKernelGGL((k_bicg_s_bj<1, T>), grid, blk, 0, s, Nn, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
     else hipLaunchKernelGGL((k_bicg_s_bj<3, T>), grid, blk, 0, s, Nn, k.r, k.v, k.s, k.sh, k.dinv, k.sc);
     if (ev) FEM_HIP(hipEventRecord(ev[2], s));
     kry_spmv<T, 2>(h, k.sh, k.t, k.s, k, 0, A, s);
     if (ev) FEM_HIP(hipEventRecord(ev[3], s));
     hipLaunchKernelGGL((k_bicg_xr<T>), grid, blk, 0, s, N, k.x, k.r, k.rh, k.ph, k.s, k.sh, k.t, k.partials, k.sc);
     hipLaunchKernelGGL(k_fin_bicg_xr, dim3(1), blk, 0, s, int(grid.x), k.partials, k.sc);
+    FEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void kry_bicg_check(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStream_t s) {
+    if (k.bj) return;  // the unfused iteration finalizes its own scalars
+    hipLaunchKernelGGL(k_bicg_check, dim3(1), dim3(kThreads), 0, s, it, k.partials2, krylov_vec_grid(h), k.sc);
     FEM_HIP(hipGetLastError());
 }
 
@@ -1205,8 +1383,10 @@ template void kry_bicg_init<double>(const fem_handle *, const KrylovVecs<double>
                                     hipStream_t);
 template void kry_cg_init<float>(const fem_handle *, const KrylovVecs<float> &, const float *, double, hipStream_t);
 template void kry_cg_init<double>(const fem_handle *, const KrylovVecs<double> &, const double *, double, hipStream_t);
-template void kry_bicg_iter<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t, hipEvent_t *);
-template void kry_bicg_iter<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t, hipEvent_t *);
+template void kry_bicg_iter<float>(const fem_handle *, const KrylovVecs<float> &, int, hipStream_t, hipEvent_t *);
+template void kry_bicg_iter<double>(const fem_handle *, const KrylovVecs<double> &, int, hipStream_t, hipEvent_t *);
+template void kry_bicg_check<float>(const fem_handle *, const KrylovVecs<float> &, int, hipStream_t);
+template void kry_bicg_check<double>(const fem_handle *, const KrylovVecs<double> &, int, hipStream_t);
 template int kry_spmv_q<float>(const fem_handle *, const KrylovVecs<float> &, hipStream_t);
 template int kry_spmv_q<double>(const fem_handle *, const KrylovVecs<double> &, hipStream_t);
 template void kry_cg_p_update<float>(const fem_handle *, const KrylovVecs<float> &, int, hipStream_t);

@@ -69,6 +69,7 @@ static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_
     w.res64 = c.take<double>(N);
     w.lam64 = c.take<double>(N);
     w.ustep = c.take<double>(N);
+    w.tmp64 = c.take<double>(N);
     w.rscr = c.take<double>(g.Ne * 8 * g.nd);
     w.ke = need_ke ? static_cast<void *>(c.take<T>(g.Ne * 64 * g.nd * g.nd)) : nullptr;
     w.values = c.take<T>(kSolverLayout == LAYOUT_SYM ? g.nnzb_up * g.nd * g.nd : g.nnz);
@@ -168,8 +169,9 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
             hipEvent_t *e = (prof && j == every / 2) ? &ev[0] : nullptr;
             if (amg) kry_cg_amg_iter<T>(h, k, it + j, s, e);
             else if (cg) kry_cg_iter<T>(h, k, it + j, s, e);
-            else kry_bicg_iter<T>(h, k, s, e);
+            else kry_bicg_iter<T>(h, k, it + j, s, e);
         }
+        if (!cg && !amg) kry_bicg_check<T>(h, k, it + every, s);
         FEM_HIP(hipMemcpyAsync(h->host_kry, w.sc, kScalarsHostBytes, hipMemcpyDeviceToHost, s));
         FEM_HIP(hipStreamSynchronize(s));
         std::memcpy(&hs, h->host_kry, kScalarsHostBytes);
@@ -230,24 +232,55 @@ static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const do
                        o.amg_smooth_degree, o.amg_coarse_degree, s);
 }
 
-// One correction: assemble K(u), solve K du = b (b already in w.b), u += du.
+// One correction: assemble K(u), solve K du = b with b = sign * r64, u += du.  Plain:
+// one Krylov solve in the solve precision to krylov_rtol on its recursive residual.
+// Mixed with opts.refine_rtol > 0: FP32 sweeps, each restarted from the FP64
+// residual b - K du of the matrix-free tangent and asked for at most a refine_rtol
+// reduction of it, until ||b - K du|| <= krylov_rtol ||b|| (the FP64 iterative
+// refinement of the correction itself).
 template <typename T>
 static int correction(fem_handle *h, SolveWork &w, double *u, const double *theta, const fem_solve_opts &o,
-                      fem_solve_stats *st, double rn, hipStream_t s) {
+                      fem_solve_stats *st, double rn, double sign, hipStream_t s) {
     const int64_t N = h->g.N;
     auto t0 = clk::now();
     assemble_into<T>(h, w, u, theta, o, s);
     check_status(h, s);
     if (st) st->ms_assemble += ms_since(t0);
     t0 = clk::now();
-    int kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, o.krylov_rtol, st, s);
-    launch_axpy_to_f64<T>(static_cast<const T *>(w.x), u, N, s);
+    int kits = 0;
+    double relres = -1.0;
+    const bool refine = sizeof(T) == 4 && o.refine_rtol > 0.0;
+    if (!refine) {
+        launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), sign, N, s);
+        kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, o.krylov_rtol, st, s);
+        launch_axpy_to_f64<T>(static_cast<const T *>(w.x), u, N, s);
+    } else {
+        // du (FP64) in lam64, the FP64 residual b - K du in res64
+        FEM_HIP(hipMemsetAsync(w.lam64, 0, N * sizeof(double), s));
+        launch_scale_cast<double, double>(w.r64, w.res64, sign, N, s);
+        const double target = o.krylov_rtol * rn;
+        double resn = rn;
+        for (int sweep = 0; resn > target && sweep < o.adjoint_max_refine; ++sweep) {
+            const double eta = std::min(0.5, std::max(o.refine_rtol, 0.5 * target / resn));
+            launch_scale_cast<T, double>(w.res64, static_cast<T *>(w.b), 1.0, N, s);
+            kits += krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, eta, st, s);
+            launch_axpy_to_f64<T>(static_cast<const T *>(w.x), w.lam64, N, s);
+            launch_apply_tangent(h, u, theta, w.lam64, w.rscr, w.tmp64, s);
+            if (sign > 0) launch_sub(w.r64, w.tmp64, w.res64, N, s);  // b - K du with b = r64
+            else launch_neg_sum(w.r64, w.tmp64, w.res64, N, s);       // b - K du with b = -r64
+            resn = norm2(h, w.res64, w, s);
+            if (!std::isfinite(resn)) throw Error(FEM_ENAN, "non-finite refinement residual");
+        }
+        relres = rn > 0.0 ? resn / rn : 0.0;
+        launch_axpy_to_f64<double>(w.lam64, u, N, s);
+    }
     FEM_HIP(hipStreamSynchronize(s));
     if (st) {
         st->ms_krylov += ms_since(t0);
         if (st->n_hist < FEM_MAX_HIST) {
             st->krylov_its[st->n_hist] = kits;
             st->residual_hist[st->n_hist] = rn;
+            if (relres >= 0.0) st->krylov_relres[st->n_hist] = relres;
             st->n_hist++;
         }
         st->newton_its++;
@@ -287,8 +320,7 @@ static void load_step(fem_handle *h, SolveWork &w, double *u, const double *thet
     int it = 0;
     if (bn > tol || fixed > 0) {
         if (o.newton_max_it < 1) throw Error(FEM_EMAXITER, "newton_max_it = 0");
-        launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), 1.0, N, s);
-        correction<T>(h, w, u, theta, o, st, bn, s);
+        correction<T>(h, w, u, theta, o, st, bn, 1.0, s);
         ++it;
     }
     launch_set_dirichlet(h, u, w.u0, gD, lam, s);
@@ -305,8 +337,7 @@ static void load_step(fem_handle *h, SolveWork &w, double *u, const double *thet
             throw Error(FEM_EMAXITER, "Newton did not converge in load step " + std::to_string(k) +
                                           " (|r| = " + sci(rn) + ", tol = " + sci(tol) + ")");
         t_it = clk::now();
-        launch_scale_cast<T, double>(w.r64, static_cast<T *>(w.b), -1.0, N, s);
-        correction<T>(h, w, u, theta, o, st, rn, s);
+        correction<T>(h, w, u, theta, o, st, rn, -1.0, s);
         t0 = clk::now();
         launch_residual(h, u, theta, lam, w.rscr, w.r64, s);
         rn = norm2(h, w.r64, w, s);
@@ -406,8 +437,10 @@ static void adjoint_impl(fem_handle *h, const double *u, const double *theta, co
         t0 = clk::now();
         launch_scale_cast<T, double>(w.res64, static_cast<T *>(w.b), 1.0, N, s);
         // Each sweep asks only for what is still missing, with a factor 2 of margin for
-        // the gap between the recursive and the true residual.
-        const double eta = std::min(0.5, std::max(o.krylov_rtol, 0.5 * tol / rn));
+        // the gap between the recursive and the true residual; with refine_rtol > 0 (mixed)
+        // it asks for at most that reduction and restarts from the FP64 residual.
+        const double floor_rtol = (sizeof(T) == 4 && o.refine_rtol > 0.0) ? o.refine_rtol : o.krylov_rtol;
+        const double eta = std::min(0.5, std::max(floor_rtol, 0.5 * tol / rn));
         int kits = krylov_solve<T>(h, w, static_cast<const T *>(w.values), o, eta, st, s);
         launch_axpy_to_f64<T>(static_cast<const T *>(w.x), w.lam64, N, s);
         if (st) {

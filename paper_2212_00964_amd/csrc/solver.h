@@ -9,6 +9,7 @@ namespace fem {
 struct SolveWork {
     double *r64 = nullptr, *u0 = nullptr, *res64 = nullptr, *lam64 = nullptr, *rscr = nullptr;
     double *ustep = nullptr;  // u at the start of a load step (restored by the load-step recovery)
+    double *tmp64 = nullptr;  // FP64 scratch vector (tangent products of the refined correction)
     void *ke = nullptr, *values = nullptr, *b = nullptr;
     void *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr,
          *ph = nullptr, *sh = nullptr, *dinv = nullptr;

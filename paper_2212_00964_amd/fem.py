@@ -60,7 +60,7 @@ class SolveOpts(ctypes.Structure):
                 ("adjoint_rtol", ctypes.c_double), ("adjoint_max_refine", ctypes.c_int32),
                 ("profile_spmv", ctypes.c_int32), ("newton_fixed_its", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("amg_smooth_degree", ctypes.c_int32), ("amg_coarse_degree", ctypes.c_int32),
-                ("max_bisections", ctypes.c_int32), ("reserved_opts", ctypes.c_int32)]
+                ("max_bisections", ctypes.c_int32), ("reserved_opts", ctypes.c_int32), ("refine_rtol", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):

@@ -310,3 +310,52 @@ def test_inverse_nh_200x100x100_forward_and_gradient_properties():
     Klam = np.array([ref[int(rr)][1] @ lh[ref[int(rr)][0]] for rr in rows])
     assert np.abs(Klam - dJdu[rows]).max() <= 1e-8 * np.linalg.norm(dJdu) + 1e-6 * np.abs(dJdu[rows]).max()
     prob.close()
+
+
+def test_inverse_nh_200x100x100_gradient_against_patch_finite_differences():
+    """Gradient of the misfit at the inverse workload's full size against central finite
+    differences.  One element moves J by about 1e-7 of itself here, below what a Newton
+    solve can resolve, so the differences perturb theta on 5 seeded 4x4x4 element patches
+    (the sum of the adjoint gradient over a patch is the derivative along that patch's
+    indicator): fourth-order stencil, relative step 1e-2, J from solves warm-started at
+    the base state and driven to the FP64 residual floor through the mixed path's FP64
+    refinement (the forward map already checked against the oracle at smaller sizes)."""
+    p, theta_true = gen.nh_inverse()
+    prob = fem.Problem(p, DEV)
+    tight = dict(precision=fem.PREC_MIXED, krylov=fem.CG, krylov_rtol=1e-3)
+    # each solve: to 1e-11, then a few more corrections down to the FP64 residual floor
+    polish = prob.opts(n_load_steps=1, newton_fixed_its=4, **tight)
+    u_obs, _ = prob.newton_solve(theta=theta_true, newton_rtol=1e-11, **tight)
+    u_obs, _ = prob.newton_solve(theta=theta_true, u0=u_obs, opts=polish)
+    u, st = prob.newton_solve(newton_rtol=1e-11, **tight)
+    u, _ = prob.newton_solve(u0=u, opts=polish)
+    free = torch.as_tensor(~p.dirichlet_mask.astype(bool), device=DEV)
+
+    def J(uu):
+        e = torch.where(free, uu - u_obs, torch.zeros_like(uu))
+        return 0.5 * float(e @ e)
+
+    dJdu = torch.where(free, u - u_obs, torch.zeros_like(u))
+    g, _, _ = prob.adjoint_vjp(u, dJdu, precision=fem.PREC_FP64, krylov=fem.CG, krylov_rtol=1e-10,
+                               adjoint_rtol=1e-11)
+    gh = host(g)
+    nx, ny, nz = p.shape
+    rng = np.random.default_rng(12)
+    fd, adj = [], []
+    fd_opts = prob.opts(n_load_steps=1, newton_fixed_its=6, **tight)
+    for _ in range(5):
+        ex, ey, ez = rng.integers(8, nx - 12), rng.integers(8, ny - 12), rng.integers(8, nz - 12)
+        idx = np.array([(ex + i) + nx * ((ey + j) + ny * (ez + k)) for k in range(4) for j in range(4) for i in range(4)])
+        h = 1e-2 * p.theta[idx[0]]
+        vals = {}
+        for kk in (-2, -1, 1, 2):
+            th = p.theta.copy()
+            th[idx] += kk * h
+            ue, _ = prob.newton_solve(theta=th, u0=u, opts=fd_opts)
+            vals[kk] = J(ue)
+        fd.append((-vals[2] + 8 * vals[1] - 8 * vals[-1] + vals[-2]) / (12 * h))
+        adj.append(gh[idx].sum())
+    fd, adj = np.array(fd), np.array(adj)
+    print(f"patch FD {fd} adjoint {adj} rel {np.abs(adj - fd) / np.abs(fd)}", flush=True)
+    assert_parity(adj, fd, 1e-5, np.abs(adj - fd) / np.abs(fd))
+    prob.close()

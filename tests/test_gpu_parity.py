@@ -267,6 +267,22 @@ def test_newton_mixed_matches_oracle(name):
     prob.close()
 
 
+@pytest.mark.parametrize("name", ["nh-9x7x6-5steps", "cantilever-7x3x5", "poisson-8cube", "nh-fan-8x4"])
+@pytest.mark.parametrize("krylov", [fem.CG, fem.BICGSTAB])
+def test_newton_mixed_refined_corrections_match_oracle(name, krylov):
+    """Mixed precision with FP64-refined corrections (FP32 Krylov sweeps restarted from
+    the matrix-free FP64 residual): the oracle's solution to the mixed bar, and each
+    correction's FP64 residual within the inner tolerance."""
+    p, lin = SOLVE_CASES[name]
+    u_ref = orc.newton_solve(p, linear=lin, rtol=1e-13)
+    prob = fem.Problem(p, DEV)
+    u, st = prob.newton_solve(precision=fem.PREC_MIXED, krylov=krylov, newton_rtol=1e-10, krylov_rtol=1e-3,
+                              refine_rtol=0.1)
+    assert_parity(host(u), u_ref, 1e-6, st.as_dict())
+    assert max(st.krylov_relres[:st.n_hist]) <= 1e-3, st.as_dict()
+    prob.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_nh_homogeneous_closed_form_on_gpu(precision):
     s, G, r = 1.2, 10.0, 10.0
