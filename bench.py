@@ -241,28 +241,39 @@ def assembly_roofline(fem, prob, u, reps=5):
                     "also writes and reads back the element blocks"}
 
 
-def j2_path(fem, inputs, n: int, nz: int, precond: int = 0) -> dict:
+def j2_path(fem, inputs, n: int, nz: int, precond: int = 0, precision: int = 0, max_bisections: int = 0,
+            time_limit_s: float = 0.0) -> dict:
     import torch
     pj = inputs.j2_cylinder(n, nz, n_load_steps=1)
     jp = fem.Problem(pj, "cuda:0")
     # iteration caps far above what the path needs (at most about 4,000 CG iterations per load step
-    # with Jacobi, 370 with the two-level preconditioner), so that a failing path ends quickly
-    jo = jp.opts(precision=fem.PREC_FP64, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-6,
-                 newton_max_it=50, krylov_max_it=20000 if precond != fem.PRECOND_AMG else 2000, precond=precond)
+    # with Jacobi, 370 with the two-level preconditioner), so that a failing path ends quickly; with
+    # the recovery on, a failed attempt must end fast, so the caps are tighter
+    recover = max_bisections > 0
+    jo = jp.opts(precision=precision, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-6,
+                 newton_max_it=15 if recover else 50,
+                 krylov_max_it=(6000 if recover else 20000) if precond != fem.PRECOND_AMG else 2000, precond=precond,
+                 max_bisections=max_bisections)
     pname = "two-level" if precond == fem.PRECOND_AMG else "Jacobi"
     gfull = torch.as_tensor(pj.dirichlet_values, dtype=torch.float64, device="cuda:0")
     uj = torch.zeros(pj.n_dofs, dtype=torch.float64, device="cuda:0")
     n_half = 10
     lam_path = [k / n_half for k in range(1, n_half + 1)] + [1.0 - k / n_half for k in range(1, n_half + 1)]
-    szz, newton_j, kry_j = [], [], []
+    szz, newton_j, kry_j, bis_j = [], [], [], []
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for lam in lam_path:
+        for step, lam in enumerate(lam_path):
+            if time_limit_s and time.perf_counter() - t0 > time_limit_s:
+                raise TimeoutError(f"stopped after {step} of {len(lam_path)} load steps ({time_limit_s:g} s budget)")
             uj, stj = jp.newton_solve(u0=uj, dirichlet_values=lam * gfull, opts=jo)
+            if recover:
+                log(f"J2 mixed path: load step {step + 1}: newton {stj.newton_its}, krylov {stj.krylov_its_total}, "
+                    f"halvings {stj.bisections}")
             szz.append(jp.average_stress()[2])
             newton_j.append(stj.newton_its)
             kry_j.append(stj.krylov_its_total)
+            bis_j.append(stj.bisections)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     finally:
@@ -270,11 +281,12 @@ def j2_path(fem, inputs, n: int, nz: int, precond: int = 0) -> dict:
     log(f"J2 path ({pname}): {dt:.2f}s ({1e3 * dt / len(lam_path):.0f} ms/load step), sigma_zz peak {max(szz):.1f} "
         f"end {szz[-1]:.1f}, newton its {sum(newton_j)}, krylov its {sum(kry_j)}")
     return {"workload": f"J2 perfect plasticity, cylinder R 5 H 10 as {n}x{n}x{nz} HEX8 ({pj.n_elems} elements, "
-                        f"{pj.n_dofs} dofs), top displacement 0 -> 0.1 -> 0 in 20 load steps, FP64 {pname}-CG "
-                        f"(inner rtol 1e-6), Newton rtol 1e-9",
+                        f"{pj.n_dofs} dofs), top displacement 0 -> 0.1 -> 0 in 20 load steps, "
+                        f"{'mixed' if precision else 'FP64'} {pname}-CG (inner rtol 1e-6), Newton rtol 1e-9"
+                        + (f", load-step recovery up to {max_bisections} halvings" if max_bisections else ""),
             "s_total": dt, "ms_per_load_step": 1e3 * dt / len(lam_path),
             "top_displacement": [0.1 * x for x in lam_path], "avg_sigma_zz": szz, "newton_its": newton_j,
-            "krylov_its": kry_j}
+            "krylov_its": kry_j, "bisections": bis_j}
 
 
 def next_rows(fem, inputs, out):
@@ -334,15 +346,43 @@ def next_rows(fem, inputs, out):
     # that the averaged stress is recorded after each.  FP64 path: past the limit load
     # the consistent tangent's smallest stiffness falls below FP32 rounding of its
     # deviatoric projection and FP32 CG meets an indefinite matrix.
-    for key, pcj in (("plasticity_path", fem.PRECOND_JACOBI), ("plasticity_path_two_level", fem.PRECOND_AMG)):
+    # FP64 (the benchmark's J2 form), and the mixed form with the load-step recovery on:
+    # past the limit load the FP32 tangent can be indefinite, which CG reports as
+    # FEM_EBREAKDOWN; the recovery halves the step up to 4 times, and the row records
+    # either the converged path or the error it ends with
+    for key, pcj, prj, nb in (("plasticity_path", fem.PRECOND_JACOBI, fem.PREC_FP64, 0),
+                              ("plasticity_path_two_level", fem.PRECOND_AMG, fem.PREC_FP64, 0),
+                              ("plasticity_path_mixed_recovery", fem.PRECOND_JACOBI, fem.PREC_MIXED, 3)):
         try:
-            out[key] = j2_path(fem, inputs, 48, 96, pcj)
-        except fem.FemError as e:
-            out[key] = {"error": str(e)}
-            log(f"J2 path failed: {e}")
+            out[key] = j2_path(fem, inputs, 48, 96, pcj, prj, nb, time_limit_s=40.0 if nb else 0.0)
+        except (fem.FemError, TimeoutError) as e:
+            out[key] = {"error": str(e), "code": getattr(e, "name", "time budget"),
+                        "form": f"{'mixed' if prj else 'FP64'} Jacobi-CG, max_bisections {nb}"}
+            log(f"J2 path ({key}) ended with {e}")
+
+
+def summarize_trace(path, out_path):
+    """Per-kernel dispatch statistics from a rocprofv3 kernel trace (CSV): count, median,
+    mean and total duration.  The median is what the profile summaries quote: Krylov
+    launches that find the solve already converged exit at once and pull the mean down."""
+    import csv
+    import collections
+    per = collections.defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            per[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    with open(out_path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Name", "Calls", "MedianUs", "MeanUs", "MinUs", "MaxUs", "TotalUs"])
+        for name, ds in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+            ds = sorted(ds)
+            w.writerow([name, len(ds), ds[len(ds) // 2], sum(ds) / len(ds), ds[0], ds[-1], sum(ds)])
 
 
 def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--summarize-trace":
+        summarize_trace(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)

@@ -907,6 +907,15 @@ __global__ __launch_bounds__(256) void k_extract_binv(int64_t Nn, const int64_t 
 constexpr int kGatherMaxDeg = 32;
 constexpr int kGatherSlots = 8;  // slots preloaded per pass
 
+// Hand-off of LDS data between lanes of one wavefront: a wavefront's LDS operations are
+// performed in program order, so a lane reads what other lanes of its wavefront wrote
+// before this point; the fence (wavefront scope) and the wave barrier keep the compiler
+// from moving LDS accesses across it.  Neither emits an instruction.
+__device__ __forceinline__ void wave_lds_handoff() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int ND, int LAYOUT, typename T>
 __global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                      const uint8_t *__restrict__ nb_bits,
@@ -941,6 +950,7 @@ __global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *
             for (int c = 0; c < ND; ++c) rowbits |= int(mask[ND * n + c] != 0) << c;
         if (lane < deg) nbm[wave][lane] = nb_bits[nb0 + lane];
         for (int l = lane; l < deg * BS; l += W) a[l] = T(0);
+        wave_lds_handoff();  // the zeroed image and the neighbour bits, to every lane
         const int64_t k1 = ne_ptr[n + 1];
         for (int64_t k0 = ne_ptr[n]; k0 < k1; k0 += kGatherSlots) {
             T val[kGatherSlots][PER];
@@ -964,14 +974,19 @@ __global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *
                     pos[kk][t] = ok ? j * BS + (lc - b * BS) : -1;
                 }
             }
+            // slot by slot: within a slot no two lanes touch one entry; a later slot's
+            // read-modify-write of an entry follows the earlier slot's
 #pragma unroll
-            for (int kk = 0; kk < kGatherSlots; ++kk)
+            for (int kk = 0; kk < kGatherSlots; ++kk) {
 #pragma unroll
                 for (int t = 0; t < PER; ++t)
                     if (pos[kk][t] >= 0) a[pos[kk][t]] += val[kk][t];
+                wave_lds_handoff();
+            }
         }
         // rows of the node, CSR (or upper blocks only), with the Dirichlet elimination
         const int jd = int(bdiag[n] - nb0);
+        wave_lds_handoff();
         bool bad = false;
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
@@ -1004,6 +1019,7 @@ __global__ __launch_bounds__(256) void k_gather_node(int64_t Nn, const int64_t *
             bad |= !invert_block<ND>(B, dinv + int64_t(BS) * n);
         }
         if (bad) atomicOr(status, ST_NAN);
+        wave_lds_handoff();  // the next node reuses the image
     }
 }
 

@@ -87,8 +87,8 @@ static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_
     w.ph = v[7];
     w.sh = v[8];
     w.dinv = v[9];
-    w.partials = c.take<double>(2 * int64_t(krylov_grid(h)));
-    w.partials2 = c.take<double>(2 * int64_t(krylov_grid(h)));
+    w.partials = c.take<double>(3 * int64_t(krylov_grid(h)));  // up to 3 sums per block
+    w.partials2 = c.take<double>(3 * int64_t(krylov_grid(h)));
     w.norm_partials = c.take<double>(krylov_grid(h));
     w.sc = c.take<KrylovScalars>(1);
     w.norm_out = c.take<double>(1);
