@@ -37,13 +37,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(prob, value_bytes):
+def spmv_bytes(prob, value_bytes, vector_bytes=None):
     """Algorithmic bytes of one Krylov SpMV launch (the node-block form): the values,
     one 32-bit column index per node block, the node row pointers, x gathered once,
     y written and one dot-product vector read."""
     nd = prob.spec.ndpn
     n_blocks = prob.nnz // (nd * nd)
-    return prob.nnz * value_bytes + n_blocks * 4 + (prob.spec.n_nodes + 1) * 8 + 3 * prob.n_dofs * value_bytes
+    vb = value_bytes if vector_bytes is None else vector_bytes
+    return prob.nnz * value_bytes + n_blocks * 4 + (prob.spec.n_nodes + 1) * 8 + 3 * prob.n_dofs * vb
 
 
 def assembly_bytes(prob, value_bytes):
@@ -361,6 +362,67 @@ def next_rows(fem, inputs, out):
             log(f"J2 path ({key}) ended with {e}")
 
 
+def linear_workload(fem, inputs, which, steps, warmup):
+    """The linear workloads (64x32x32 cantilever, FP64 vs mixed; 120x60x30 SIMP cantilever):
+    the full solve to a 1e-9 relative residual and the adjoint gradient (J = 1/2 |u_free|^2,
+    or the compliance F.u for SIMP) in every form, each timed over `steps` repetitions."""
+    import torch
+    p = inputs.workload(2 if which == "cantilever" else 4)
+    prob = fem.Problem(p, "cuda:0")
+    log(f"workload {p.name}: {p.n_elems} elements, {p.n_dofs} dofs, nnz {prob.nnz}")
+    F = prob.load_vector()
+    ref_o = prob.opts(precision=fem.PREC_FP64, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-11, krylov_rtol=1e-10,
+                      adjoint_rtol=1e-11, adjoint_max_refine=20)
+    u_ref, _ = prob.newton_solve(opts=ref_o)
+
+    def dJdu_of(u):
+        return F.clone() if which == "simp" else torch.where(prob.mask, torch.zeros_like(u), u)
+
+    g_ref, _, _ = prob.adjoint_vjp(u_ref, dJdu_of(u_ref), opts=ref_o, want_lambda=False)
+    rows = {}
+    for name, prec, kry in (("fp64-cg", fem.PREC_FP64, fem.CG), ("mixed-cg", fem.PREC_MIXED, fem.CG),
+                            ("mixed64-cg", fem.PREC_MIXED_V64, fem.CG),
+                            ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB),
+                            ("mixed-bicgstab", fem.PREC_MIXED, fem.BICGSTAB),
+                            ("mixed64-bicgstab", fem.PREC_MIXED_V64, fem.BICGSTAB)):
+        rr = refine_for(fem, prec, kry)
+        so = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-3, refine_rtol=rr,
+                       krylov_max_it=20000)
+        ao = prob.opts(precision=prec, krylov=kry, krylov_rtol=1e-3, adjoint_rtol=adjoint_rtol_for(fem, kry, None),
+                       refine_rtol=rr, adjoint_max_refine=60, krylov_max_it=20000)
+        solve_ms, grad_ms = [], []
+        try:
+            for k in range(warmup + steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u, st = prob.newton_solve(opts=so)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                g, _, sa = prob.adjoint_vjp(u, dJdu_of(u), opts=ao, want_lambda=False)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                if k >= warmup:
+                    solve_ms.append(1e3 * (t1 - t0))
+                    grad_ms.append(1e3 * (t2 - t1))
+        except fem.FemError as e:  # recorded: the other forms still run
+            rows[name] = {"error": str(e)}
+            log(f"{name}: {e}")
+            continue
+        rows[name] = {"solve_ms": float(np.median(solve_ms)), "grad_ms": float(np.median(grad_ms)),
+                      "newton_its": st.newton_its, "krylov_its": st.krylov_its_total,
+                      "adjoint_krylov_its": sa.krylov_its_total,
+                      "u_rel_err": float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref)),
+                      "grad_rel_err": float(torch.linalg.norm(g - g_ref) / torch.linalg.norm(g_ref))}
+        log(f"{name}: solve {rows[name]['solve_ms']:.1f} ms ({st.krylov_its_total} its), gradient "
+            f"{rows[name]['grad_ms']:.1f} ms ({sa.krylov_its_total} its), errors {rows[name]['u_rel_err']:.1e} / "
+            f"{rows[name]['grad_rel_err']:.1e}")
+    prob.close()
+    print(json.dumps({"workload": f"{p.name} ({p.n_elems} elements, {p.n_dofs} dofs, nnz {prob.nnz}); solve to a 1e-9 "
+                                  f"relative residual and the adjoint gradient of "
+                                  + ("the compliance F.u" if which == "simp" else "J = 1/2 |u_free|^2"),
+                      "steps": steps, "warmup": warmup, "forms": rows}), flush=True)
+
+
 def summarize_trace(path, out_path):
     """Per-kernel dispatch statistics from a rocprofv3 kernel trace (CSV): count, median,
     mean and total duration.  The median is what the profile summaries quote: Krylov
@@ -387,11 +449,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["nh100", "inverse"], default="nh100",
+    ap.add_argument("--workload", choices=["nh100", "inverse", "cantilever", "simp"], default="nh100",
                     help="nh100: the 100^3 neo-Hookean block (the benchmark line); inverse: the 200x100x100 "
-                         "inverse-modulus block (misfit objective)")
+                         "inverse-modulus block (misfit objective); cantilever / simp: the linear 64x32x32 and "
+                         "120x60x30 workloads, every form (a JSON line of their own)")
     ap.add_argument("--size", type=int, nargs=3, default=None)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "mixed64", "fp64"], default="mixed64",
+                    help="mixed: FP32 tangent and FP32 Krylov vectors; mixed64: FP32 tangent under FP64 Krylov "
+                         "vectors; fp64")
     ap.add_argument("--krylov", choices=["cg", "bicgstab"], default="bicgstab",
                     help="Krylov method of the timed step (the workload names Jacobi-BiCGSTAB)")
     ap.add_argument("--precond", choices=["jacobi", "block-jacobi", "two-level"], default="jacobi",
@@ -417,6 +482,9 @@ def main():
     from paper_2212_00964_amd import fem, inputs
 
     torch.cuda.set_device(0)
+    if args.workload in ("cantilever", "simp"):
+        linear_workload(fem, inputs, args.workload, args.steps, args.warmup)
+        return
     if args.workload == "inverse":
         nx, ny, nz = args.size or (200, 100, 100)
         p, theta_true = inputs.nh_inverse(nx, ny, nz)
@@ -427,7 +495,7 @@ def main():
     t0 = time.perf_counter()
     prob = fem.Problem(p, "cuda:0")
     log(f"pattern + upload {time.perf_counter() - t0:.1f}s, nnz={prob.nnz}")
-    prec = fem.PREC_MIXED if args.precision == "mixed" else fem.PREC_FP64
+    prec = {"mixed": fem.PREC_MIXED, "mixed64": fem.PREC_MIXED_V64, "fp64": fem.PREC_FP64}[args.precision]
     kry = fem.CG if args.krylov == "cg" else fem.BICGSTAB
     pc = {"jacobi": fem.PRECOND_JACOBI, "block-jacobi": fem.PRECOND_BLOCK_JACOBI,
           "two-level": fem.PRECOND_AMG}[args.precond]
@@ -437,7 +505,7 @@ def main():
         o = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_fixed_its=1, krylov_rtol=1e-12,
                       krylov_max_it=64, check_every=64, precond=pc)
         u, _ = prob.newton_solve(dirichlet_values=0.2 * g_final, opts=o)
-        prob.assemble(u, residual=False, values_dtype=torch.float32 if prec == fem.PREC_MIXED else torch.float64)
+        prob.assemble(u, residual=False, values_dtype=torch.float64 if prec == fem.PREC_FP64 else torch.float32)
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0").fill_(1.0)
         b = torch.empty_like(a)
         b.copy_(a)  # 256 MiB read + 256 MiB written: calibrates FETCH_SIZE / WRITE_SIZE
@@ -473,9 +541,9 @@ def main():
     log(f"timed: {main_form['wall_ms']:.2f} ms/step; median Newton iteration {t_step:.2f} ms "
         f"(iterations {[round(x, 1) for x in main_form['iter_ms']]} ms, Krylov its {main_form['krylov_its']}), "
         f"adjoint {t_grad:.2f} ms ({main_form['adjoint_krylov_its']} its, {main_form['adjoint_sweeps']} sweeps)")
-    vb = 4 if prec == fem.PREC_MIXED else 8
+    vb = 8 if prec == fem.PREC_FP64 else 4
     avg_spmv_ms = main_form["spmv_ms"] / max(main_form["spmv_calls"], 1)
-    nbytes = spmv_bytes(prob, vb)
+    nbytes = spmv_bytes(prob, vb, 8 if prec != fem.PREC_MIXED else 4)
     achieved = nbytes / (avg_spmv_ms * 1e-3) / 1e9
     log(f"SpMV: {main_form['spmv_calls']} timed launches, avg {avg_spmv_ms * 1e3:.1f} us, {achieved:.0f} GB/s")
     kname = "k_spmv_nodes (Krylov SpMV + FP64 dot)"
@@ -485,7 +553,9 @@ def main():
         "metric": METRIC, "value": t_step + t_grad, "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": main_form["wall_ms"], "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 tangent/SpMV/Krylov + f64 residual/dots" if prec == fem.PREC_MIXED else "f64",
+        "dtype": {fem.PREC_MIXED: "f32 tangent/SpMV/Krylov + f64 residual/dots",
+                  fem.PREC_MIXED_V64: "f32 tangent values + f64 Krylov vectors/SpMV arithmetic/residual",
+                  fem.PREC_FP64: "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": (f"neo-Hookean tensile block {nx}x{ny}x{nz} HEX8 ({p.n_elems} elements, {p.n_dofs} "
                                 f"dofs, nnz {prob.nnz}), lognormal G (ln 10, 0.3), kappa = 10 G, load step 5 of 5 to "
@@ -512,7 +582,8 @@ def main():
                      "launch_sampling": "HIP events around the SpMVs of the middle Krylov iteration of every "
                                         "16-iteration check block, over the timed steps",
                      "bytes_per_launch": nbytes,
-                     "bytes_definition": "nnz*v + nnz/9*4 (one int32 per 3x3 block) + (Nn+1)*8 + 3*N*v"},
+                     "bytes_definition": "nnz*v + nnz/9*4 (one int32 per 3x3 block) + (Nn+1)*8 + 3*N*w "
+                                         "(v: bytes per stored value, w: per vector entry)"},
     }
     out["roofline_assembly"] = assembly_roofline(fem, prob, main_form["u5"])
     log(f"assembly: {out['roofline_assembly']['avg_launch_us']:.0f} us, frac {out['roofline_assembly']['frac']:.3f}")
@@ -544,9 +615,10 @@ def main():
                        "adjoint_krylov_its": f["adjoint_krylov_its"], "adjoint_sweeps": f["adjoint_sweeps"]}
         log(f"fp64 {args.krylov} step: {f['t_step']:.1f} + {f['t_grad']:.1f} ms, "
             f"speedup of mixed {out['fp64_step']['speedup_mixed_over_fp64']:.2f}x")
-        other = (("cg_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI),
-                 ("bicgstab_step", fem.PREC_MIXED, fem.BICGSTAB, fem.PRECOND_JACOBI),
-                 ("block_jacobi_step", fem.PREC_MIXED, kry, fem.PRECOND_BLOCK_JACOBI),
+        other = (("mixed_f32_vectors_step", fem.PREC_MIXED, kry, fem.PRECOND_JACOBI),
+                 ("cg_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI),
+                 ("bicgstab_step", prec, fem.BICGSTAB, fem.PRECOND_JACOBI),
+                 ("block_jacobi_step", prec, kry, fem.PRECOND_BLOCK_JACOBI),
                  ("two_level_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG))
         for key, pr, kr, pcn in other:
             if (pr, kr, pcn) == (prec, kry, pc):
@@ -555,9 +627,16 @@ def main():
                 t0 = time.perf_counter()
                 n_agg, n_cb = prob.amg_sizes()
                 t_setup = time.perf_counter() - t0
-            r = measure(pr, kr, pcn, 2, 1)
+            try:
+                r = measure(pr, kr, pcn, 2, 1)
+            except fem.FemError as e:  # recorded, not fatal: the other rows still run
+                out[key] = {"error": str(e)}
+                log(f"{key}: {e}")
+                continue
             out[key] = row(r)
-            out[key]["form"] = ("mixed " + {0: "jacobi", 1: "block-jacobi", 2: "two-level"}[pcn] + "-"
+            out[key]["form"] = ({fem.PREC_FP64: "fp64 ", fem.PREC_MIXED: "mixed (FP32 vectors) ",
+                                 fem.PREC_MIXED_V64: "mixed64 (FP64 vectors) "}[pr]
+                                + {0: "jacobi", 1: "block-jacobi", 2: "two-level"}[pcn] + "-"
                                 + ("cg" if kr == fem.CG else "bicgstab"))
             if pcn == fem.PRECOND_AMG:
                 out[key].update({"aggregates": n_agg, "coarse_blocks": n_cb, "setup_s": t_setup})
@@ -567,7 +646,8 @@ def main():
         u_ref, _ = prob.newton_solve(opts=prob.opts(precision=fem.PREC_FP64, krylov=fem.CG, krylov_rtol=1e-8,
                                                     newton_rtol=1e-11))
         res = {}
-        forms = (("mixed-bicgstab", fem.PREC_MIXED, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.5),
+        forms = (("mixed64-bicgstab", fem.PREC_MIXED_V64, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.0),
+                 ("mixed-bicgstab", fem.PREC_MIXED, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.5),
                  ("mixed-bicgstab-one-solve-per-correction", fem.PREC_MIXED, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.0),
                  ("mixed-cg", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI, 0.0),
                  ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.0),
@@ -575,19 +655,26 @@ def main():
                  ("mixed-cg-two-level", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG, 0.0))
         for name, pr, kr, pcn, rr in forms:
             o = prob.opts(precision=pr, krylov=kr, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol, precond=pcn,
-                          refine_rtol=rr)
+                          refine_rtol=rr, max_bisections=4)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            u, st = prob.newton_solve(opts=o)
+            try:
+                u, st = prob.newton_solve(opts=o)
+            except fem.FemError as e:
+                res[name] = {"error": str(e), "refine_rtol": rr}
+                log(f"full 5-step solve {name}: {e}")
+                continue
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             err = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
             res[name] = {"s": dt, "newton_its": st.newton_its, "krylov_its": st.krylov_its_total,
-                         "rel_err_vs_tight_fp64": err, "refine_rtol": rr}
+                         "rel_err_vs_tight_fp64": err, "refine_rtol": rr, "bisections": st.bisections}
             log(f"full 5-step solve {name}: {dt:.2f}s newton_its={st.newton_its} krylov_its={st.krylov_its_total} "
                 f"err={err:.2e}")
-        res["speedup_mixed_over_fp64_bicgstab"] = res["fp64-bicgstab"]["s"] / res["mixed-bicgstab"]["s"]
-        res["speedup_mixed_over_fp64_cg"] = res["fp64-cg"]["s"] / res["mixed-cg"]["s"]
+        for a, b in (("fp64-bicgstab", "mixed64-bicgstab"), ("fp64-bicgstab", "mixed-bicgstab"),
+                     ("fp64-cg", "mixed-cg")):
+            if "s" in res[a] and "s" in res[b]:
+                res[f"speedup_{b}_over_{a}".replace("-", "_")] = res[a]["s"] / res[b]["s"]
         out["full_solve"] = res
         if u_obs is None:
             next_rows(fem, inputs, out)

@@ -84,8 +84,13 @@ enum { FEM_LAYOUT_CSR = 0, FEM_LAYOUT_SYM_BLOCK = 1 };
 /* FEM_PREC_FP64: tangent, SpMV and Krylov vectors in FP64.
  * FEM_PREC_MIXED: tangent values, SpMV and Krylov vectors in FP32 with FP32
  * accumulation; the Newton/refinement residual, the adjoint refinement residual
- * and all Krylov inner products stay FP64. */
-enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1 };
+ * and all Krylov inner products stay FP64.
+ * FEM_PREC_MIXED_V64: the tangent is assembled and stored in FP32 (the SpMV streams
+ * FP32 values, the bulk of its bytes), while the Krylov vectors, the SpMV's products
+ * and sums and every vector update are FP64: the Krylov method runs in FP64 on the
+ * fixed FP32 operator.  Residuals and refinement as in FEM_PREC_MIXED.  Jacobi and
+ * node-block Jacobi only (FEM_EINVAL with FEM_PRECOND_AMG). */
+enum { FEM_PREC_FP64 = 0, FEM_PREC_MIXED = 1, FEM_PREC_MIXED_V64 = 2 };
 enum { FEM_KRYLOV_CG = 0, FEM_KRYLOV_BICGSTAB = 1 };
 /* Krylov preconditioner.  FEM_PRECOND_JACOBI: the inverse diagonal of the tangent
  * (the paper's Jacobi preconditioner, Sec. 5).  FEM_PRECOND_BLOCK_JACOBI: the
@@ -128,7 +133,7 @@ typedef struct {
 } fem_mesh_desc;
 
 typedef struct {
-    int32_t precision;      /* FEM_PREC_FP64 or FEM_PREC_MIXED */
+    int32_t precision;      /* FEM_PREC_FP64, FEM_PREC_MIXED or FEM_PREC_MIXED_V64 */
     int32_t krylov;         /* FEM_KRYLOV_CG (SPD tangents) or FEM_KRYLOV_BICGSTAB */
     int32_t n_load_steps;   /* >= 1 */
     int32_t newton_max_it;  /* per load step */
@@ -291,8 +296,9 @@ int fem_apply_tangent(fem_handle *h, const double *u, const double *theta, const
  * FP64 residual, assembles K(u), solves K du = -r with the Jacobi-preconditioned
  * Krylov method of opts (Sec. 5, item 2) and updates u.  A step stops when
  * ||r_free|| <= max(newton_rtol * max(||first right-hand side||, ||F_k||), atol).  In
- * FEM_PREC_MIXED the correction solve runs in FP32 and the FP64 residual of the next
- * iteration performs the refinement.  u [N] FP64 is in/out.  Blocks; returns
+ * FEM_PREC_MIXED the correction solve runs in FP32 (in FEM_PREC_MIXED_V64 with FP64
+ * vectors on the FP32 tangent) and the FP64 residual of the next iteration performs
+ * the refinement.  u [N] FP64 is in/out.  Blocks; returns
  * FEM_EMAXITER / FEM_EDIVERGED / FEM_EBREAKDOWN / FEM_EMESH / FEM_EINVERTED / FEM_ENAN
  * on failure (u then holds the last iterate).  `stats` may be NULL. */
 int fem_newton_solve(fem_handle *h, double *u, const double *theta, const double *dirichlet_values,
@@ -303,8 +309,9 @@ int fem_newton_solve(fem_handle *h, double *u, const double *theta, const double
  * solves (dC/du)^T lambda = dJdu with Dirichlet entries of the right-hand side set
  * to 0, then writes vjp_theta[e] = -lambda^T dC/dtheta_e [n_elems] FP64.  u is the
  * converged state.  lambda_out [N] may be NULL.  In FEM_PREC_MIXED the transposed
- * solve runs in FP32 inside FP64 iterative refinement whose residual uses the
- * matrix-free FP64 tangent.  Blocks. */
+ * solve runs in FP32 (FEM_PREC_MIXED_V64: FP64 vectors on the FP32 tangent) inside
+ * FP64 iterative refinement whose residual uses the matrix-free FP64 tangent.
+ * Blocks. */
 int fem_adjoint_vjp(fem_handle *h, const double *u, const double *theta, const double *dJdu, double *vjp_theta,
                     double *lambda_out, const fem_solve_opts *opts, fem_solve_stats *stats, void *workspace,
                     size_t workspace_bytes, void *stream);

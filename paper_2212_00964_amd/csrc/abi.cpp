@@ -42,7 +42,8 @@ void bind_device(const fem_handle *h) { FEM_HIP(hipSetDevice(h->device)); }
 
 void validate_opts(const fem_solve_opts *o) {
     require(o != nullptr, "opts is NULL");
-    require(o->precision == FEM_PREC_FP64 || o->precision == FEM_PREC_MIXED, "opts.precision");
+    require(o->precision == FEM_PREC_FP64 || o->precision == FEM_PREC_MIXED || o->precision == FEM_PREC_MIXED_V64,
+            "opts.precision");
     require(o->krylov == FEM_KRYLOV_CG || o->krylov == FEM_KRYLOV_BICGSTAB, "opts.krylov");
     require(o->n_load_steps >= 1, "opts.n_load_steps must be >= 1");
     require(o->newton_max_it >= 0 && o->krylov_max_it >= 1 && o->check_every >= 1, "opts iteration limits");
@@ -57,6 +58,7 @@ void validate_opts(const fem_solve_opts *o) {
             "opts.precond");
     if (o->precond == FEM_PRECOND_AMG) {
         require(o->krylov == FEM_KRYLOV_CG, "FEM_PRECOND_AMG needs FEM_KRYLOV_CG");
+        require(o->precision != FEM_PREC_MIXED_V64, "FEM_PRECOND_AMG takes FEM_PREC_FP64 or FEM_PREC_MIXED");
         require(o->amg_smooth_degree >= 1 && o->amg_smooth_degree <= 64, "opts.amg_smooth_degree must be in [1, 64]");
         require(o->amg_coarse_degree >= 1 && o->amg_coarse_degree <= 64, "opts.amg_coarse_degree must be in [1, 64]");
     }

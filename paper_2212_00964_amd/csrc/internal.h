@@ -238,6 +238,7 @@ struct KrylovVecs {
     double *partials;   // per-block partial sums written by one kernel ...
     double *partials2;  // ... and by the next one (the two alternate)
     KrylovScalars *sc;
+    const float *A32 = nullptr;  // FP32 values under FP64 vectors (A unused then)
 };
 
 template <typename T>

@@ -16,6 +16,7 @@
 // Paper: BiCGSTAB with a Jacobi preconditioner is the linear solver inside Newton
 // (Sec. 5, item 2; van der Vorst 1992).
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "lanes.h"
@@ -188,15 +189,17 @@ constexpr int kSpmvGroup = 32;
 constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
 
 // Nodes in flight per 32-lane group: as many as fit with the double-buffered loads
-// at an occupancy of four (FP32) or two (FP64) wavefronts per SIMD.
-template <int ND, typename T>
-constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(T) == 4 ? 4 : 2); }
+// at an occupancy of four (FP32 values) or two (FP64 values) wavefronts per SIMD.
+// TV is the type of the stored values (FP32 values under FP64 vectors: the mixed
+// form with FP64 Krylov vectors, three nodes in flight, as four would spill).
+template <int ND, typename TV, typename T = TV>
+constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(TV) == 4 ? (sizeof(T) == 4 ? 4 : 3) : 2); }
 
-template <int ND, int P, int MODE, typename T, bool D16>
-__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
+template <int ND, int P, int MODE, typename T, bool D16, typename TV = T>
+__global__ __launch_bounds__(kThreads, sizeof(TV) == 4 ? 4 : 2) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                          const int32_t *__restrict__ node_nb,
                                                          const int16_t *__restrict__ node_dnb,
-                                                         const T *__restrict__ values, const T *__restrict__ x,
+                                                         const TV *__restrict__ values, const T *__restrict__ x,
                                                          T *__restrict__ y, const T *__restrict__ w0, T alpha,
                                                          T beta, double *partials, KrylovScalars *sc, int cg,
                                                          int big) {
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
         int64_t b0[P];
         int deg[P];
         int32_t m[P];
-        T v[P][ND][ND];
+        TV v[P][ND][ND];
         // Column indices and values of P nodes.  Addresses are clamped (a slot past the
         // chunk re-reads its last node, a lane past the degree reads block 0), so the
         // loads are branch-free; the results of such slots are masked.
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
                     m[p] = int32_t(n0 + ln) + int32_t(__builtin_nontemporal_load(node_dnb + b0[p] + lc));
                 else
                     m[p] = __builtin_nontemporal_load(node_nb + b0[p] + lc);
-                const T *vb = values + int64_t(ND) * ND * b0[p] + ND * lc;
+                const TV *vb = values + int64_t(ND) * ND * b0[p] + ND * lc;
 #pragma unroll
                 for (int i = 0; i < ND; ++i)
 #pragma unroll
@@ -253,7 +256,8 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
             // Software pipeline: the x gathers of this batch go out first, then the next
             // batch's index and value loads, so waiting for the gathers leaves the next
             // batch in flight (memory counters complete in issue order).
-            T xm[P][ND], cv[P][ND][ND];
+            T xm[P][ND];
+            TV cv[P][ND][ND];
             int cdeg[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
                 for (int i = 0; i < ND; ++i) {
                     T a = T(0);
 #pragma unroll
-                    for (int k = 0; k < ND; ++k) a += cv[p][i][k] * xm[p][k];
+                    for (int k = 0; k < ND; ++k) a += T(cv[p][i][k]) * xm[p][k];
                     acc[i] = lane < cdeg[p] ? a : T(0);
                 }
                 T sv;
@@ -294,11 +298,11 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 2) void k_spmv_nodes
                 for (int i = 0; i < ND; ++i) acc[i] = T(0);
                 for (int l = lane + G; l < dg; l += G) {
                     const int64_t mm = node_nb[b + l];
-                    const T *vb = values + int64_t(ND) * ND * b + ND * l;
+                    const TV *vb = values + int64_t(ND) * ND * b + ND * l;
 #pragma unroll
                     for (int i = 0; i < ND; ++i)
 #pragma unroll
-                        for (int k = 0; k < ND; ++k) acc[i] += vb[int64_t(i) * ND * dg + k] * x[ND * mm + k];
+                        for (int k = 0; k < ND; ++k) acc[i] += T(vb[int64_t(i) * ND * dg + k]) * x[ND * mm + k];
                 }
                 T sv;
                 if constexpr (ND == 3) sv = group32_sum3(acc[0], acc[1], acc[2], lane);
@@ -1274,24 +1278,28 @@ void kry_cg_init(const fem_handle *h, const KrylovVecs<T> &k, const T *b, double
 
 // Launches the fused SpMV (partials into k.partials) and, unless the caller folds it
 // into its next kernel, the one-block finalize; returns the SpMV grid size.
-template <int ND, int P, int MODE, typename T>
+template <int ND, int P, int MODE, typename T, typename TV = T>
 static int kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
-                           const T *values, bool finalize, hipStream_t s) {
+                           const TV *values, bool finalize, hipStream_t s) {
     const Graph &g = h->g;
     int G;
     if (k.layout == LAYOUT_SYM) {
-        G = resident_grid(h, k_spmv_sym<ND, P, MODE, T>);
-        hipLaunchKernelGGL((k_spmv_sym<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.up_base,
-                           g.node_nb, g.lo_val, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
+        if constexpr (std::is_same<T, TV>::value) {
+            G = resident_grid(h, k_spmv_sym<ND, P, MODE, T>);
+            hipLaunchKernelGGL((k_spmv_sym<ND, P, MODE, T>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
+                               g.up_base, g.node_nb, g.lo_val, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg);
+        } else {
+            throw Error(FEM_EINVAL, "the symmetric block layout takes values of the vector type");
+        }
     } else if (g.node_dnb) {
-        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T, true>);
-        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T, true>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
-                           g.node_nb, g.node_dnb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
+        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T, true, TV>);
+        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T, true, TV>), dim3(G), dim3(kThreads), 0, s, g.Nn,
+                           g.node_ptr, g.node_nb, g.node_dnb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
                            int(g.max_deg > kSpmvGroup));
     } else {
-        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T, false>);
-        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T, false>), dim3(G), dim3(kThreads), 0, s, g.Nn, g.node_ptr,
-                           g.node_nb, g.node_dnb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
+        G = resident_grid(h, k_spmv_nodes<ND, P, MODE, T, false, TV>);
+        hipLaunchKernelGGL((k_spmv_nodes<ND, P, MODE, T, false, TV>), dim3(G), dim3(kThreads), 0, s, g.Nn,
+                           g.node_ptr, g.node_nb, g.node_dnb, values, x, y, w0, T(1), T(0), k.partials, k.sc, cg,
                            int(g.max_deg > kSpmvGroup));
     }
     if (finalize) {
@@ -1301,9 +1309,20 @@ static int kry_spmv_launch(const fem_handle *h, const T *x, T *y, const T *w0, c
     return G;
 }
 
+// The Krylov SpMV on the solve's operator: k.A, or the FP32 tangent k.A32 under FP64
+// vectors (products and sums in FP64).
 template <typename T, int MODE>
 static int kry_spmv(const fem_handle *h, const T *x, T *y, const T *w0, const KrylovVecs<T> &k, int cg,
                     const T *values, hipStream_t s, bool finalize = true) {
+    if constexpr (sizeof(T) == 8) {
+        if (k.A32) {
+            if (h->g.nd == 1)
+                return kry_spmv_launch<1, spmv_batch<1, float, T>(), MODE, T, float>(h, x, y, w0, k, cg, k.A32,
+                                                                                     finalize, s);
+            return kry_spmv_launch<3, spmv_batch<3, float, T>(), MODE, T, float>(h, x, y, w0, k, cg, k.A32, finalize,
+                                                                                 s);
+        }
+    }
     if (h->g.nd == 1) return kry_spmv_launch<1, spmv_batch<1, T>(), MODE, T>(h, x, y, w0, k, cg, values, finalize, s);
     return kry_spmv_launch<3, spmv_batch<3, T>(), MODE, T>(h, x, y, w0, k, cg, values, finalize, s);
 }

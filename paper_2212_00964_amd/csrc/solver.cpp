@@ -60,10 +60,12 @@ static std::string sci(double v) {
     return buf;
 }
 
+// v32 (FEM_PREC_MIXED_V64, T = double): element blocks and values in FP32.
 template <typename T>
-static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_ke) {
+static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_ke, bool v32 = false) {
     const Graph &g = h->g;
     const int64_t N = g.N;
+    const int64_t nvals = kSolverLayout == LAYOUT_SYM ? g.nnzb_up * g.nd * g.nd : g.nnz;
     w.r64 = c.take<double>(N);
     w.u0 = c.take<double>(N);
     w.res64 = c.take<double>(N);
@@ -71,8 +73,15 @@ static void carve_solve(Carver &c, const fem_handle *h, SolveWork &w, bool need_
     w.ustep = c.take<double>(N);
     w.tmp64 = c.take<double>(N);
     w.rscr = c.take<double>(g.Ne * 8 * g.nd);
-    w.ke = need_ke ? static_cast<void *>(c.take<T>(g.Ne * 64 * g.nd * g.nd)) : nullptr;
-    w.values = c.take<T>(kSolverLayout == LAYOUT_SYM ? g.nnzb_up * g.nd * g.nd : g.nnz);
+    w.v32 = v32;
+    if (v32) {
+        w.ke = need_ke ? static_cast<void *>(c.take<float>(g.Ne * 64 * g.nd * g.nd)) : nullptr;
+        w.values = c.take<float>(nvals);
+        w.dinv32 = c.take<float>(g.Nn * g.nd * g.nd);
+    } else {
+        w.ke = need_ke ? static_cast<void *>(c.take<T>(g.Ne * 64 * g.nd * g.nd)) : nullptr;
+        w.values = c.take<T>(nvals);
+    }
     w.b = c.take<T>(N);
     T *v[10];
     for (int i = 0; i < 9; ++i) v[i] = c.take<T>(N);
@@ -103,7 +112,7 @@ size_t solve_workspace_bytes(const fem_handle *h, const fem_solve_opts *o) {
         return c.used;
     }
     if (o->precision == FEM_PREC_MIXED) carve_solve<float>(c, h, w, true);
-    else carve_solve<double>(c, h, w, true);
+    else carve_solve<double>(c, h, w, true, o->precision == FEM_PREC_MIXED_V64);
     return c.used;
 }
 
@@ -143,6 +152,11 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
                     w.partials,
                     w.partials2,
                     w.sc};
+    if constexpr (sizeof(T) == 8)
+        if (w.v32) {  // the FP32 tangent under FP64 vectors
+            k.A = nullptr;
+            k.A32 = static_cast<const float *>(w.values);
+        }
     const bool cg = o.krylov == FEM_KRYLOV_CG;
     const bool amg = o.precond == FEM_PRECOND_AMG;  // CG only (checked at the ABI)
     const T *b = static_cast<const T *>(w.b);
@@ -225,6 +239,16 @@ static double ms_since(clk::time_point t0) {
 template <typename T>
 static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const double *theta,
                           const fem_solve_opts &o, hipStream_t s) {
+    if (w.v32) {
+        if (o.precond == FEM_PRECOND_AMG)
+            throw Error(FEM_EINVAL, "the two-level preconditioner takes FP32 or FP64 vectors, not FEM_PREC_MIXED_V64");
+        launch_tangent<float>(h, u, theta, static_cast<float *>(w.ke), static_cast<float *>(w.values), w.dinv32, s,
+                              kSolverLayout, o.precond);
+        const int64_t nd = h->g.nd;
+        launch_scale_cast<double, float>(w.dinv32, static_cast<double *>(w.dinv), 1.0,
+                                         o.precond == FEM_PRECOND_BLOCK_JACOBI ? h->g.Nn * nd * nd : h->g.N, s);
+        return;
+    }
     launch_tangent<T>(h, u, theta, static_cast<T *>(w.ke), static_cast<T *>(w.values), static_cast<T *>(w.dinv), s,
                       kSolverLayout, o.precond);
     if (o.precond == FEM_PRECOND_AMG)  // the coarse operator and bounds of this tangent
@@ -365,7 +389,7 @@ static void newton_impl(fem_handle *h, double *u, const double *theta, const dou
                         fem_solve_stats *st, void *ws, size_t wsb, hipStream_t s) {
     Carver c(ws, wsb, false);
     SolveWork w;
-    carve_solve<T>(c, h, w, true);
+    carve_solve<T>(c, h, w, true, o.precision == FEM_PREC_MIXED_V64);
     const int64_t N = h->g.N;
     auto t_all = clk::now();
     reset_status(h, s);
@@ -414,7 +438,7 @@ static void adjoint_impl(fem_handle *h, const double *u, const double *theta, co
                          hipStream_t s) {
     Carver c(ws, wsb, false);
     SolveWork w;
-    carve_solve<T>(c, h, w, true);
+    carve_solve<T>(c, h, w, true, o.precision == FEM_PREC_MIXED_V64);
     const int64_t N = h->g.N;
     auto t_all = clk::now();
     reset_status(h, s);
@@ -480,7 +504,7 @@ static void amg_apply_impl(fem_handle *h, const double *u, const double *theta, 
                            hipStream_t s) {
     Carver c(ws, wsb, false);
     SolveWork w;
-    carve_solve<T>(c, h, w, true);
+    carve_solve<T>(c, h, w, true, o.precision == FEM_PREC_MIXED_V64);
     const int64_t N = h->g.N;
     reset_status(h, s);
     assemble_into<T>(h, w, u, theta, o, s);

@@ -15,6 +15,10 @@ struct SolveWork {
          *ph = nullptr, *sh = nullptr, *dinv = nullptr;
     double *partials = nullptr, *partials2 = nullptr, *norm_partials = nullptr, *norm_out = nullptr;
     KrylovScalars *sc = nullptr;
+    // FEM_PREC_MIXED_V64: ke and values hold FP32 under FP64 vectors; the gather writes
+    // the FP32 preconditioner to dinv32, cast into dinv
+    bool v32 = false;
+    float *dinv32 = nullptr;
 };
 
 size_t solve_workspace_bytes(const fem_handle *h, const fem_solve_opts *o);

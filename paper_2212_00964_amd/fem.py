@@ -24,7 +24,7 @@ ERRORS = {-1: "FEM_EINVAL", -2: "FEM_ERANGE", -3: "FEM_EHIP", -4: "FEM_EMESH", -
           -6: "FEM_ENAN", -7: "FEM_EBREAKDOWN", -8: "FEM_EMAXITER", -9: "FEM_EDIVERGED", -10: "FEM_ENOMEM"}
 F32, F64 = 0, 1
 LAYOUT_CSR, LAYOUT_SYM_BLOCK = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_V64 = 0, 1, 2
 CG, BICGSTAB = 0, 1
 PRECOND_JACOBI, PRECOND_BLOCK_JACOBI, PRECOND_AMG = 0, 1, 2
 FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1

@@ -283,7 +283,31 @@ def test_newton_mixed_refined_corrections_match_oracle(name, krylov):
     prob.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", list(SOLVE_CASES))
+@pytest.mark.parametrize("krylov", [fem.CG, fem.BICGSTAB])
+@pytest.mark.parametrize("precond", [fem.PRECOND_JACOBI, fem.PRECOND_BLOCK_JACOBI])
+def test_newton_mixed_v64_matches_oracle(name, krylov, precond):
+    """FP32 tangent under FP64 Krylov vectors: the oracle's solution to the mixed bar."""
+    p, lin = SOLVE_CASES[name]
+    u_ref = orc.newton_solve(p, linear=lin, rtol=1e-13)
+    prob = fem.Problem(p, DEV)
+    u, st = prob.newton_solve(precision=fem.PREC_MIXED_V64, krylov=krylov, precond=precond, newton_rtol=1e-10,
+                              krylov_rtol=1e-5)
+    assert_parity(host(u), u_ref, 1e-6, st.as_dict())
+    prob.close()
+
+
+def test_mixed_v64_refuses_the_two_level_preconditioner():
+    p = CASES["nh-5x3x7-lognormal"]
+    prob = fem.Problem(p, DEV)
+    prob.amg_setup()
+    with pytest.raises(fem.FemError) as e:
+        prob.newton_solve(precision=fem.PREC_MIXED_V64, krylov=fem.CG, precond=fem.PRECOND_AMG)
+    assert e.value.name == "FEM_EINVAL"
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_nh_homogeneous_closed_form_on_gpu(precision):
     s, G, r = 1.2, 10.0, 10.0
     p = gen.nh_roller_uniaxial(5, 4, 3, stretch=s, G=G, bulk_ratio=r, n_load_steps=4, distort_seed=8)
@@ -334,7 +358,7 @@ def test_block_jacobi_reduces_iterations_and_matches_point_jacobi():
 # ----------------------------------------------------------------------------- adjoint
 
 @pytest.mark.parametrize("name", ["nh-5x3x7-lognormal", "nh-fan-8x4"])
-@pytest.mark.parametrize("precision,tol", [(0, 1e-8), (1, 1e-5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-8), (1, 1e-5), (2, 1e-5)])
 def test_adjoint_matches_oracle(precision, tol, name):
     p = CASES[name]
     u_ref = orc.newton_solve(p, rtol=1e-13)
