@@ -496,6 +496,8 @@ def main():
     prob = fem.Problem(p, "cuda:0")
     log(f"pattern + upload {time.perf_counter() - t0:.1f}s, nnz={prob.nnz}")
     prec = {"mixed": fem.PREC_MIXED, "mixed64": fem.PREC_MIXED_V64, "fp64": fem.PREC_FP64}[args.precision]
+    if args.precond == "two-level" and prec == fem.PREC_MIXED_V64:
+        raise SystemExit("the two-level preconditioner runs with --precision mixed or fp64")
     kry = fem.CG if args.krylov == "cg" else fem.BICGSTAB
     pc = {"jacobi": fem.PRECOND_JACOBI, "block-jacobi": fem.PRECOND_BLOCK_JACOBI,
           "two-level": fem.PRECOND_AMG}[args.precond]
@@ -654,6 +656,10 @@ def main():
                  ("fp64-cg", fem.PREC_FP64, fem.CG, fem.PRECOND_JACOBI, 0.0),
                  ("mixed-cg-two-level", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG, 0.0))
         for name, pr, kr, pcn, rr in forms:
+            if pcn == fem.PRECOND_AMG and "error" in out.get("two_level_step", {}):
+                res[name] = {"skipped": "the two-level step above failed: " + out["two_level_step"]["error"]}
+                log(f"full 5-step solve {name}: skipped (the two-level step failed)")
+                continue
             o = prob.opts(precision=pr, krylov=kr, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol, precond=pcn,
                           refine_rtol=rr, max_bisections=4)
             torch.cuda.synchronize()

@@ -190,13 +190,18 @@ constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
 
 // Nodes in flight per 32-lane group: as many as fit with the double-buffered loads
 // at an occupancy of four (FP32 values) or two (FP64 values) wavefronts per SIMD.
-// TV is the type of the stored values (FP32 values under FP64 vectors: the mixed
-// form with FP64 Krylov vectors, three nodes in flight, as four would spill).
+// TV is the type of the stored values.  FP32 values under FP64 vectors (the mixed form
+// with FP64 Krylov vectors): four nodes at three wavefronts per SIMD (149 registers;
+// measured 243 us per launch at the 100^3 workload against 254 us with three nodes at
+// four wavefronts, which fit in 128).
 template <int ND, typename TV, typename T = TV>
-constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(TV) == 4 ? (sizeof(T) == 4 ? 4 : 3) : 2); }
+constexpr int spmv_batch() { return ND == 1 ? 4 : (sizeof(TV) == 4 ? 4 : 2); }
+
+template <typename TV, typename T>
+constexpr int spmv_waves() { return sizeof(TV) == 4 ? (sizeof(T) == 4 ? 4 : 3) : 2; }
 
 template <int ND, int P, int MODE, typename T, bool D16, typename TV = T>
-__global__ __launch_bounds__(kThreads, sizeof(TV) == 4 ? 4 : 2) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
+__global__ __launch_bounds__(kThreads, (spmv_waves<TV, T>())) void k_spmv_nodes(int64_t Nn, const int64_t *__restrict__ node_ptr,
                                                          const int32_t *__restrict__ node_nb,
                                                          const int16_t *__restrict__ node_dnb,
                                                          const TV *__restrict__ values, const T *__restrict__ x,
