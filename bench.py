@@ -173,7 +173,7 @@ def adjoint_rtol_for(fem, kry, given):
 
 
 def measure_form(fem, prob, u4, prec, kry, pc, krylov_rtol, adjoint_rtol, steps, warmup, profile=False,
-                 u_obs=None):
+                 u_obs=None, krylov_max_it=20000, newton_max_it=50):
     """Load step 5 solved from the converged state of load step 4 (every Newton
     iteration timed) and the adjoint gradient at its solution of J = 1/2 |u_free|^2, or of
     the misfit J = 1/2 |u_free - u_obs|^2 when u_obs is given.
@@ -181,11 +181,13 @@ def measure_form(fem, prob, u4, prec, kry, pc, krylov_rtol, adjoint_rtol, steps,
     import torch
     rr = refine_for(fem, prec, kry)
     adjoint_rtol = adjoint_rtol_for(fem, kry, adjoint_rtol)
-    step_o = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_rtol=1e-9, newton_max_it=50,
-                       krylov_rtol=krylov_rtol, profile_spmv=int(profile), precond=pc, refine_rtol=rr)
+    step_o = prob.opts(precision=prec, krylov=kry, n_load_steps=1, newton_rtol=1e-9, newton_max_it=newton_max_it,
+                       krylov_rtol=krylov_rtol, profile_spmv=int(profile), precond=pc, refine_rtol=rr,
+                       krylov_max_it=krylov_max_it)
     # sweeps that each halve the residual need about 20 for 1e-6: leave room
     adj_o = prob.opts(precision=prec, krylov=kry, krylov_rtol=krylov_rtol, adjoint_rtol=adjoint_rtol,
-                      profile_spmv=int(profile), precond=pc, refine_rtol=rr, adjoint_max_refine=60)
+                      profile_spmv=int(profile), precond=pc, refine_rtol=rr, adjoint_max_refine=60,
+                      krylov_max_it=krylov_max_it)
 
     def one():
         u5, sn = prob.newton_solve(u0=u4, opts=step_o)
@@ -534,9 +536,9 @@ def main():
     def objective_grad(u5):
         return torch.where(prob.mask, torch.zeros_like(u5), u5 if u_obs is None else u5 - u_obs)
 
-    def measure(pr, kr, pcn, steps, warmup, profile=False):
+    def measure(pr, kr, pcn, steps, warmup, profile=False, krylov_max_it=20000, newton_max_it=50):
         return measure_form(fem, prob, u4, pr, kr, pcn, args.krylov_rtol, args.adjoint_rtol, steps, warmup, profile,
-                            u_obs=u_obs)
+                            u_obs=u_obs, krylov_max_it=krylov_max_it, newton_max_it=newton_max_it)
 
     main_form = measure(prec, kry, pc, args.steps, args.warmup, profile=True)
     t_step, t_grad = main_form["t_step"], main_form["t_grad"]
@@ -621,7 +623,10 @@ def main():
                  ("cg_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI),
                  ("bicgstab_step", prec, fem.BICGSTAB, fem.PRECOND_JACOBI),
                  ("block_jacobi_step", prec, kry, fem.PRECOND_BLOCK_JACOBI),
-                 ("two_level_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG))
+                 # on the inverse block the stored FP32 tangent is not positive definite along
+                 # the smooth modes that the two-level CG finds (p.Kp <= 0 after 159-1216
+                 # iterations, or thousands of iterations without it), so that row runs in FP64
+                 ("two_level_step", fem.PREC_MIXED if u_obs is None else fem.PREC_FP64, fem.CG, fem.PRECOND_AMG))
         for key, pr, kr, pcn in other:
             if (pr, kr, pcn) == (prec, kry, pc):
                 continue
@@ -630,7 +635,8 @@ def main():
                 n_agg, n_cb = prob.amg_sizes()
                 t_setup = time.perf_counter() - t0
             try:
-                r = measure(pr, kr, pcn, 2, 1)
+                amg = pcn == fem.PRECOND_AMG  # bounded, so that a failing two-level solve ends within minutes
+                r = measure(pr, kr, pcn, 2, 1, krylov_max_it=2000 if amg else 20000, newton_max_it=12 if amg else 50)
             except fem.FemError as e:  # recorded, not fatal: the other rows still run
                 out[key] = {"error": str(e)}
                 log(f"{key}: {e}")
@@ -654,14 +660,16 @@ def main():
                  ("mixed-cg", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI, 0.0),
                  ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.0),
                  ("fp64-cg", fem.PREC_FP64, fem.CG, fem.PRECOND_JACOBI, 0.0),
-                 ("mixed-cg-two-level", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG, 0.0))
+                 ("mixed-cg-two-level" if u_obs is None else "fp64-cg-two-level",
+                  fem.PREC_MIXED if u_obs is None else fem.PREC_FP64, fem.CG, fem.PRECOND_AMG, 0.0))
         for name, pr, kr, pcn, rr in forms:
             if pcn == fem.PRECOND_AMG and "error" in out.get("two_level_step", {}):
                 res[name] = {"skipped": "the two-level step above failed: " + out["two_level_step"]["error"]}
                 log(f"full 5-step solve {name}: skipped (the two-level step failed)")
                 continue
             o = prob.opts(precision=pr, krylov=kr, newton_rtol=1e-9, krylov_rtol=args.krylov_rtol, precond=pcn,
-                          refine_rtol=rr, max_bisections=4)
+                          refine_rtol=rr, max_bisections=4,
+                          krylov_max_it=2000 if pcn == fem.PRECOND_AMG else 20000)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             try:

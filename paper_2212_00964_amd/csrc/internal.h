@@ -239,6 +239,7 @@ struct KrylovVecs {
     double *partials2;  // ... and by the next one (the two alternate)
     KrylovScalars *sc;
     const float *A32 = nullptr;  // FP32 values under FP64 vectors (A unused then)
+    int fold = 0;  // 1: point Jacobi folded into the values (BiCGSTAB on K D^{-1}; its iterate y, x = D^{-1} y)
 };
 
 template <typename T>
@@ -301,6 +302,11 @@ template <typename TO, typename TI>
 void launch_scale_cast(const TI *in, TO *out, double alpha, int64_t n, hipStream_t s);
 template <typename TI>
 void launch_axpy_to_f64(const TI *x, double *y, int64_t n, hipStream_t s);
+// values of column dof j *= dinv[j] (CSR layout of the node graph)
+template <typename T>
+void launch_scale_columns(const fem_handle *h, T *values, const T *dinv, hipStream_t s);
+template <typename T>
+void launch_mul_inplace(T *x, const T *d, int64_t n, hipStream_t s);
 void launch_set_dirichlet(const fem_handle *h, double *u, const double *u0, const double *g, double lam,
                           hipStream_t s);
 // delta = (u0 + lam (g - u0) - u) on Dirichlet dofs, 0 elsewhere

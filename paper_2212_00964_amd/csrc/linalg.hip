@@ -710,7 +710,9 @@ __device__ __forceinline__ void bicg_publish_start(const BicgStart &b, KrylovSca
     else if (b.div) sc->breakdown = 1;
 }
 
-template <typename T>
+// FOLD: the point-Jacobi scaling sits in the stored operator (K D^{-1}, see
+// k_scale_columns), so the SpMV inputs are p and s themselves and ph, sh are not written.
+template <typename T, bool FOLD = false>
 __global__ __launch_bounds__(kThreads) void k_bicg_p_fused(int64_t N, int it, const T *__restrict__ r,
                                                            T *__restrict__ p, const T *__restrict__ v,
                                                            T *__restrict__ ph, T *__restrict__ rh,
@@ -747,7 +749,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_p_fused(int64_t N, int it, co
         const typename V::type rv = V::ld(r, i);
         const typename V::type pv = restart ? rv : rv + bt * (V::ld(p, i) - om * V::ld(v, i));
         V::st(p, i, pv);
-        V::st(ph, i, V::ld(dinv, i) * pv);
+        if (!FOLD) V::st(ph, i, V::ld(dinv, i) * pv);
         if (restart) V::st(rh, i, rv);
     }
     if (blockIdx.x == 0)
@@ -755,12 +757,12 @@ __global__ __launch_bounds__(kThreads) void k_bicg_p_fused(int64_t N, int it, co
             const T ri = r[i];
             const T pi = restart ? ri : ri + bt * (p[i] - om * v[i]);
             p[i] = pi;
-            ph[i] = dinv[i] * pi;
+            if (!FOLD) ph[i] = dinv[i] * pi;
             if (restart) rh[i] = ri;
         }
 }
 
-template <typename T>
+template <typename T, bool FOLD = false>
 __global__ __launch_bounds__(kThreads) void k_bicg_s_fused(int64_t N, int it, const T *__restrict__ r,
                                                            const T *__restrict__ v, T *__restrict__ s,
                                                            T *__restrict__ sh, const T *__restrict__ dinv,
@@ -785,17 +787,17 @@ __global__ __launch_bounds__(kThreads) void k_bicg_s_fused(int64_t N, int it, co
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads) {
         const typename V::type sv = V::ld(r, i) - al * V::ld(v, i);
         V::st(s, i, sv);
-        V::st(sh, i, V::ld(dinv, i) * sv);
+        if (!FOLD) V::st(sh, i, V::ld(dinv, i) * sv);
     }
     if (blockIdx.x == 0)
         for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) {
             const T si = r[i] - al * v[i];
             s[i] = si;
-            sh[i] = dinv[i] * si;
+            if (!FOLD) sh[i] = dinv[i] * si;
         }
 }
 
-template <typename T>
+template <typename T, bool FOLD = false>
 __global__ __launch_bounds__(kThreads) void k_bicg_xr_fused(int64_t N, int it, T *__restrict__ x, T *__restrict__ r,
                                                             const T *__restrict__ rh, const T *__restrict__ ph,
                                                             const T *__restrict__ s, const T *__restrict__ sh,
@@ -821,8 +823,9 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr_fused(int64_t N, int it, T
     constexpr int W = V::W;
     const int64_t NV = N / W;
     for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < NV; i += int64_t(gridDim.x) * kThreads) {
-        V::st(x, i, V::ld(x, i) + al * V::ld(ph, i) + om * V::ld(sh, i));
-        const typename V::type rv = V::ld(s, i) - om * V::ld(t, i);
+        const typename V::type sv = V::ld(s, i);
+        V::st(x, i, V::ld(x, i) + al * V::ld(ph, i) + om * (FOLD ? sv : V::ld(sh, i)));
+        const typename V::type rv = sv - om * V::ld(t, i);
         const typename V::type hv = V::ld(rh, i);
         V::st(r, i, rv);
 #pragma unroll
@@ -833,8 +836,9 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr_fused(int64_t N, int it, T
     }
     if (blockIdx.x == 0)
         for (int64_t i = NV * W + threadIdx.x; i < N; i += kThreads) {
-            x[i] += al * ph[i] + om * sh[i];
-            const T ri = s[i] - om * t[i];
+            const T si = s[i];
+            x[i] += al * ph[i] + om * (FOLD ? si : sh[i]);
+            const T ri = si - om * t[i];
             r[i] = ri;
             d0 += double(rh[i]) * double(ri);
             d1 += double(ri) * double(ri);
@@ -1377,18 +1381,32 @@ void kry_bicg_iter(const fem_handle *h, const KrylovVecs<T> &k, int it, hipStrea
     const int64_t Nn = h->g.Nn;
     if (!k.bj) {
         dim3 grid(krylov_vec_grid(h)), blk(kThreads);
-        hipLaunchKernelGGL((k_bicg_p_fused<T>), grid, blk, 0, s, N, it, k.r, k.p, k.v, k.ph, k.rh, k.dinv,
-                           k.partials2, int(grid.x), k.sc);
+        // folded Jacobi: the operator is K D^{-1} and the SpMVs take p and s directly
+        T *ph = k.fold ? k.p : k.ph, *sh = k.fold ? k.s : k.sh;
+        if (k.fold)
+            hipLaunchKernelGGL((k_bicg_p_fused<T, true>), grid, blk, 0, s, N, it, k.r, k.p, k.v, ph, k.rh, k.dinv,
+                               k.partials2, int(grid.x), k.sc);
+        else
+            hipLaunchKernelGGL((k_bicg_p_fused<T, false>), grid, blk, 0, s, N, it, k.r, k.p, k.v, ph, k.rh, k.dinv,
+                               k.partials2, int(grid.x), k.sc);
         if (ev) FEM_HIP(hipEventRecord(ev[0], s));
-        int G = kry_spmv<T, 1>(h, k.ph, k.v, k.rh, k, 0, A, s, false);
+        int G = kry_spmv<T, 1>(h, ph, k.v, k.rh, k, 0, A, s, false);
         if (ev) FEM_HIP(hipEventRecord(ev[1], s));
-        hipLaunchKernelGGL((k_bicg_s_fused<T>), grid, blk, 0, s, N, it, k.r, k.v, k.s, k.sh, k.dinv, k.partials, G,
-                           k.sc);
+        if (k.fold)
+            hipLaunchKernelGGL((k_bicg_s_fused<T, true>), grid, blk, 0, s, N, it, k.r, k.v, k.s, sh, k.dinv,
+                               k.partials, G, k.sc);
+        else
+            hipLaunchKernelGGL((k_bicg_s_fused<T, false>), grid, blk, 0, s, N, it, k.r, k.v, k.s, sh, k.dinv,
+                               k.partials, G, k.sc);
         if (ev) FEM_HIP(hipEventRecord(ev[2], s));
-        G = kry_spmv<T, 2>(h, k.sh, k.t, k.s, k, 0, A, s, false);
+        G = kry_spmv<T, 2>(h, sh, k.t, k.s, k, 0, A, s, false);
         if (ev) FEM_HIP(hipEventRecord(ev[3], s));
-        hipLaunchKernelGGL((k_bicg_xr_fused<T>), grid, blk, 0, s, N, it, k.x, k.r, k.rh, k.ph, k.s, k.sh, k.t,
-                           k.partials, G, k.partials2, k.sc);
+        if (k.fold)
+            hipLaunchKernelGGL((k_bicg_xr_fused<T, true>), grid, blk, 0, s, N, it, k.x, k.r, k.rh, ph, k.s, sh, k.t,
+                               k.partials, G, k.partials2, k.sc);
+        else
+            hipLaunchKernelGGL((k_bicg_xr_fused<T, false>), grid, blk, 0, s, N, it, k.x, k.r, k.rh, ph, k.s, sh, k.t,
+                               k.partials, G, k.partials2, k.sc);
         FEM_HIP(hipGetLastError());
         return;
     }
@@ -1482,6 +1500,65 @@ void launch_scale_cast(const TI *in, TO *out, double alpha, int64_t n, hipStream
 template void launch_scale_cast<float, double>(const double *, float *, double, int64_t, hipStream_t);
 template void launch_scale_cast<double, double>(const double *, double *, double, int64_t, hipStream_t);
 template void launch_scale_cast<double, float>(const float *, double *, double, int64_t, hipStream_t);
+
+// Right point-Jacobi scaling folded into the stored tangent: every value of column
+// dof j is multiplied by dinv[j], so BiCGSTAB runs on K D^{-1} (the same iterates as
+// right preconditioning with D, without the D^{-1} p and D^{-1} s vectors), and its
+// iterate y maps back as x = D^{-1} y.  One 32-lane group per node, lane = block.
+template <int ND, typename T>
+__global__ __launch_bounds__(kThreads) void k_scale_columns(int64_t Nn, const int64_t *__restrict__ node_ptr,
+                                                            const int32_t *__restrict__ node_nb,
+                                                            T *__restrict__ values, const T *__restrict__ dinv) {
+    constexpr int G = 32;
+    const int lane = threadIdx.x % G;
+    for (int64_t n = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / G; n < Nn;
+         n += int64_t(gridDim.x) * (kThreads / G)) {
+        const int64_t b0 = node_ptr[n];
+        const int deg = int(node_ptr[n + 1] - b0);
+        for (int l = lane; l < deg; l += G) {
+            const int64_t m = node_nb[b0 + l];
+            T d[ND];
+#pragma unroll
+            for (int c = 0; c < ND; ++c) d[c] = dinv[ND * m + c];
+            T *vb = values + int64_t(ND) * ND * b0 + ND * l;
+#pragma unroll
+            for (int i = 0; i < ND; ++i)
+#pragma unroll
+                for (int c = 0; c < ND; ++c) vb[int64_t(i) * ND * deg + c] *= d[c];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_mul_inplace(int64_t n, T *__restrict__ x, const T *__restrict__ d) {
+    for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += int64_t(gridDim.x) * kThreads)
+        x[i] *= d[i];
+}
+
+template <typename T>
+void launch_scale_columns(const fem_handle *h, T *values, const T *dinv, hipStream_t s) {
+    const Graph &g = h->g;
+    if (g.Nn == 0) return;
+    dim3 grid(grid_for(g.Nn, kThreads / 32));
+    if (g.nd == 1)
+        hipLaunchKernelGGL((k_scale_columns<1, T>), grid, dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values,
+                           dinv);
+    else
+        hipLaunchKernelGGL((k_scale_columns<3, T>), grid, dim3(kThreads), 0, s, g.Nn, g.node_ptr, g.node_nb, values,
+                           dinv);
+    FEM_HIP(hipGetLastError());
+}
+template void launch_scale_columns<float>(const fem_handle *, float *, const float *, hipStream_t);
+template void launch_scale_columns<double>(const fem_handle *, double *, const double *, hipStream_t);
+
+template <typename T>
+void launch_mul_inplace(T *x, const T *d, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_mul_inplace<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, n, x, d);
+    FEM_HIP(hipGetLastError());
+}
+template void launch_mul_inplace<float>(float *, const float *, int64_t, hipStream_t);
+template void launch_mul_inplace<double>(double *, const double *, int64_t, hipStream_t);
 
 template <typename TI>
 void launch_axpy_to_f64(const TI *x, double *y, int64_t n, hipStream_t s) {

@@ -23,6 +23,13 @@ constexpr size_t kAlign = 256;
 // ~245 us for the full CSR layout), so the solvers use CSR.
 constexpr int kSolverLayout = LAYOUT_CSR;
 
+// Point-Jacobi BiCGSTAB folds D^{-1} into the stored tangent (right preconditioning
+// applied to the values once per assembly), which removes the D^{-1} p and D^{-1} s
+// vectors from every iteration.
+bool fold_jacobi(const fem_solve_opts &o) {
+    return o.krylov == FEM_KRYLOV_BICGSTAB && o.precond == FEM_PRECOND_JACOBI;
+}
+
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Bump allocator over the caller's workspace.
@@ -152,6 +159,7 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
                     w.partials,
                     w.partials2,
                     w.sc};
+    k.fold = fold_jacobi(o) ? 1 : 0;
     if constexpr (sizeof(T) == 8)
         if (w.v32) {  // the FP32 tangent under FP64 vectors
             k.A = nullptr;
@@ -211,6 +219,7 @@ int krylov_solve(fem_handle *h, SolveWork &w, const T *A, const fem_solve_opts &
         }
         if (it + every >= o.krylov_max_it) break;
     }
+    if (k.fold) launch_mul_inplace<T>(k.x, k.dinv, h->g.N, s);  // x = D^{-1} y
     const double relres = hs.bnorm2 > 0.0 ? std::sqrt(hs.rnorm2 / hs.bnorm2) : 0.0;
     if (st) {
         st->krylov_its_total += hs.its;
@@ -244,6 +253,7 @@ static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const do
             throw Error(FEM_EINVAL, "the two-level preconditioner takes FP32 or FP64 vectors, not FEM_PREC_MIXED_V64");
         launch_tangent<float>(h, u, theta, static_cast<float *>(w.ke), static_cast<float *>(w.values), w.dinv32, s,
                               kSolverLayout, o.precond);
+        if (fold_jacobi(o)) launch_scale_columns<float>(h, static_cast<float *>(w.values), w.dinv32, s);
         const int64_t nd = h->g.nd;
         launch_scale_cast<double, float>(w.dinv32, static_cast<double *>(w.dinv), 1.0,
                                          o.precond == FEM_PRECOND_BLOCK_JACOBI ? h->g.Nn * nd * nd : h->g.N, s);
@@ -251,6 +261,7 @@ static void assemble_into(fem_handle *h, SolveWork &w, const double *u, const do
     }
     launch_tangent<T>(h, u, theta, static_cast<T *>(w.ke), static_cast<T *>(w.values), static_cast<T *>(w.dinv), s,
                       kSolverLayout, o.precond);
+    if (fold_jacobi(o)) launch_scale_columns<T>(h, static_cast<T *>(w.values), static_cast<const T *>(w.dinv), s);
     if (o.precond == FEM_PRECOND_AMG)  // the coarse operator and bounds of this tangent
         amg_refresh<T>(h, static_cast<const T *>(w.values), static_cast<const T *>(w.dinv), o.precision,
                        o.amg_smooth_degree, o.amg_coarse_degree, s);
