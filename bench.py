@@ -5,7 +5,9 @@ Workload: compressible neo-Hookean block, 100x100x100 HEX8 on the unit cube
 (1,000,000 elements, 3,090,903 dofs), per-element shear modulus lognormal
 (mu = ln 10, sigma = 0.3, seed 0), bulk modulus 10x shear, pulled to stretch 1.2
 in 5 load steps, Newton with Jacobi-preconditioned BiCGSTAB in mixed precision (the
-workload's named form; --krylov cg for Jacobi-CG).
+workload's named form: the tangent assembled and stored in FP32, the Krylov vectors in
+FP64, FP64 residuals and refinement; --precision mixed keeps the Krylov vectors in
+FP32, --precision fp64 is the plain FP64 form, --krylov cg for Jacobi-CG).
 
 One timed step solves load step 5 from the converged state of load step 4 (every
 Newton iteration timed: FP64 residual, Dirichlet lifting, tangent assembly, Jacobi
@@ -271,7 +273,7 @@ def j2_path(fem, inputs, n: int, nz: int, precond: int = 0, precision: int = 0, 
                 raise TimeoutError(f"stopped after {step} of {len(lam_path)} load steps ({time_limit_s:g} s budget)")
             uj, stj = jp.newton_solve(u0=uj, dirichlet_values=lam * gfull, opts=jo)
             if recover:
-                log(f"J2 mixed path: load step {step + 1}: newton {stj.newton_its}, krylov {stj.krylov_its_total}, "
+                log(f"J2 path with recovery: load step {step + 1}: newton {stj.newton_its}, krylov {stj.krylov_its_total}, "
                     f"halvings {stj.bisections}")
             szz.append(jp.average_stress()[2])
             newton_j.append(stj.newton_its)
