@@ -216,17 +216,8 @@ __device__ __forceinline__ bool flux_mat(const Material &m, T mod, const T G[3][
 #pragma unroll
             for (int j = 0; j < 3; ++j) P[i][j] = mu * (G[i][j] + G[j][i]) + (i == j ? lam * tr : T(0));
         return true;
-    } else if constexpr (MODEL == FEM_J2_PLASTIC) {  // the returned stress of the point
-        J2State<T> s;
-        j2_state(m, mod, G, hq, s);
-        const int ix[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) P[i][j] = s.sig[ix[i][j]];
-        return true;
     } else {
-        static_assert(MODEL == FEM_NEO_HOOKEAN, "unknown law");
+        static_assert(MODEL == FEM_NEO_HOOKEAN, "the J2 law uses j2_flux_dot");
         NHState<T> s;
         bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
 #pragma unroll
@@ -243,24 +234,8 @@ __device__ __forceinline__ bool dflux_mat(const Material &m, T mod, const T G[3]
                                           const double *hq) {
     if constexpr (MODEL == FEM_POISSON || MODEL == FEM_LINEAR_ELASTIC) {
         return flux_mat<MODEL, T>(m, mod, dG, dP, hq);  // linear laws
-    } else if constexpr (MODEL == FEM_J2_PLASTIC) {  // the consistent tangent A : dG
-        J2State<T> s;
-        j2_state(m, mod, G, hq, s);
-        const int ix[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-        const T tr = dG[0][0] + dG[1][1] + dG[2][2];
-        T sd = T(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) sd += s.dev[ix[i][j]] * dG[i][j];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                dP[i][j] = (i == j ? s.lw * tr : T(0)) + s.mup * (dG[i][j] + dG[j][i]) - s.beta * sd * s.dev[ix[i][j]];
-        return true;
     } else {
-        static_assert(MODEL == FEM_NEO_HOOKEAN, "unknown law");
+        static_assert(MODEL == FEM_NEO_HOOKEAN, "the J2 law uses j2_dflux_dot");
         NHState<T> s;
         bool ok = nh_state(G, mod, T(m.bulk_ratio), s);
         T HdF = T(0), FdF = T(0);
@@ -384,10 +359,6 @@ enum { VEC_RESIDUAL = 0, VEC_JVP = 1, VEC_VJP = 2, VEC_LIFT = 3, VEC_MASS = 4 };
 // Lane a then sums its node's terms, sum_q M_q dN_a(xi_q) (= sum_q detJ P g_a).  The
 // per-point work (Jacobian inverse, constitutive update) is done once per point
 // instead of once per lane.
-// The J2 law in the per-point form of the kernel below (one constitutive update per
-// Gauss point) instead of the per-lane form (every lane repeats the 8 updates).
-constexpr bool kJ2PerPoint = false;
-
 template <int MODEL, int ND, int MODE>
 __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const double *__restrict__ coords,
                                                           const int32_t *__restrict__ conn,
@@ -399,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
                                                           const double *__restrict__ hist, double *__restrict__ out,
                                                           int *status) {
     constexpr bool kDir = MODE == VEC_JVP || MODE == VEC_LIFT;
-    if constexpr (MODEL == FEM_J2_PLASTIC && !kJ2PerPoint) {
+    if constexpr (MODEL == FEM_J2_PLASTIC) {
         // J2 keeps the per-lane form (every lane walks the 8 points for its own node): the
         // loading-unloading path near the limit load has a nearly singular tangent, and
         // its Newton iterations were measured to converge with this form's rounding.
@@ -492,9 +463,8 @@ __global__ __launch_bounds__(kThreads) void k_element_vec(int64_t Ne, const doub
                 G[i][j] = Gr[i][0] * Bt[j][0] + Gr[i][1] * Bt[j][1] + Gr[i][2] * Bt[j][2];
                 dG[i][j] = Wr[i][0] * Bt[j][0] + Wr[i][1] * Bt[j][1] + Wr[i][2] * Bt[j][2];
             }
-        const double *hq = (MODEL == FEM_J2_PLASTIC) ? hist + (id.e * 8 + q) * 12 : nullptr;
-        if constexpr (kDir) mat_ok = dflux_mat<MODEL, double>(mat, mod, G, dG, P, hq);
-        else mat_ok = flux_mat<MODEL, double>(mat, mod, G, P, hq);
+        if constexpr (kDir) mat_ok = dflux_mat<MODEL, double>(mat, mod, G, dG, P, nullptr);
+        else mat_ok = flux_mat<MODEL, double>(mat, mod, G, P, nullptr);
         double *mq = Ms[id.el][q];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
