@@ -625,10 +625,7 @@ def main():
                  ("cg_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI),
                  ("bicgstab_step", prec, fem.BICGSTAB, fem.PRECOND_JACOBI),
                  ("block_jacobi_step", prec, kry, fem.PRECOND_BLOCK_JACOBI),
-                 # on the inverse block the stored FP32 tangent is not positive definite along
-                 # the smooth modes that the two-level CG finds (p.Kp <= 0 after 159-1216
-                 # iterations, or thousands of iterations without it), so that row runs in FP64
-                 ("two_level_step", fem.PREC_MIXED if u_obs is None else fem.PREC_FP64, fem.CG, fem.PRECOND_AMG))
+                 ("two_level_step", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG))
         for key, pr, kr, pcn in other:
             if (pr, kr, pcn) == (prec, kry, pc):
                 continue
@@ -662,8 +659,7 @@ def main():
                  ("mixed-cg", fem.PREC_MIXED, fem.CG, fem.PRECOND_JACOBI, 0.0),
                  ("fp64-bicgstab", fem.PREC_FP64, fem.BICGSTAB, fem.PRECOND_JACOBI, 0.0),
                  ("fp64-cg", fem.PREC_FP64, fem.CG, fem.PRECOND_JACOBI, 0.0),
-                 ("mixed-cg-two-level" if u_obs is None else "fp64-cg-two-level",
-                  fem.PREC_MIXED if u_obs is None else fem.PREC_FP64, fem.CG, fem.PRECOND_AMG, 0.0))
+                 ("mixed-cg-two-level", fem.PREC_MIXED, fem.CG, fem.PRECOND_AMG, 0.0))
         for name, pr, kr, pcn, rr in forms:
             if pcn == fem.PRECOND_AMG and "error" in out.get("two_level_step", {}):
                 res[name] = {"skipped": "the two-level step above failed: " + out["two_level_step"]["error"]}

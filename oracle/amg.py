@@ -20,12 +20,13 @@ reading, taken identically by the GPU path):
   columns (6 per aggregate), so A_c = P^T A P, with a unit diagonal entry for every
   dropped column.
 * Chebyshev iteration on D^{-1} A (Saad, "Iterative Methods for Sparse Linear
-  Systems", 2nd ed., Alg. 12.1) on the interval [lmax / 30, lmax]; lmax is 1.2 times
-  the power estimate ||D^{-1} A x|| / ||x|| after 12 normalised steps from
-  x_i = sin(1 + i), capped by the Gershgorin bound max_i sum_j |A_ij| / A_ii (an upper
-  bound of the spectrum; the power estimate alone approaches the top of the spectrum
-  from below, and an interval that misses it amplifies those modes).  The same for the
-  coarse operator with its own diagonal and estimate.
+  Systems", 2nd ed., Alg. 12.1) on the interval [lmax / 30, lmax].  On the fine level
+  lmax is the Gershgorin bound max_i sum_j |A_ij| / |A_ii|, an upper bound of the
+  spectrum: an interval that misses the top of the spectrum amplifies those modes and
+  makes the preconditioner indefinite.  On the coarse level, whose polynomial has a
+  higher degree and is hurt more by a loose interval, lmax is 1.2 times the power
+  estimate ||D^{-1} A x|| / ||x|| after 12 normalised steps from x_i = sin(1 + i),
+  capped by the coarse operator's Gershgorin bound.
 * One application z = M r: pre-smoothing (`smooth_degree` Chebyshev steps from 0),
   the residual r - A z restricted by P^T, the coarse correction (`coarse_degree`
   Chebyshev steps from 0 on A_c), prolongation by P, and post-smoothing
@@ -132,6 +133,11 @@ def coarse_operator(A, P, dropped):
     return Ac.tocsr()
 
 
+def gershgorin_bound(A, dinv):
+    """max_i |dinv_i| sum_j |A_ij|: the row-sum norm of D^{-1} A, which bounds its spectrum."""
+    return float(np.max(np.asarray(abs(A).sum(axis=1)).ravel() * np.abs(dinv)))
+
+
 def lmax_estimate(A, dinv):
     x = np.sin(1.0 + np.arange(A.shape[0], dtype=np.float64))
     x /= np.linalg.norm(x)
@@ -140,8 +146,7 @@ def lmax_estimate(A, dinv):
         y = dinv * (A @ x)
         lam = np.linalg.norm(y)  # ||x|| = 1
         x = y / lam
-    gersh = float(np.max(np.asarray(abs(A).sum(axis=1)).ravel() * np.abs(dinv)))
-    return min(LMAX_SAFETY * lam, gersh)
+    return min(LMAX_SAFETY * lam, gershgorin_bound(A, dinv))
 
 
 def chebyshev(A, dinv, r, lmax, degree, z=None):
@@ -178,7 +183,7 @@ class TwoLevel:
         self.Ac = coarse_operator(self.A, self.P, self.dropped)
         self.dinv = 1.0 / self.A.diagonal()
         self.dcinv = 1.0 / self.Ac.diagonal()
-        self.lmax = lmax_estimate(self.A, self.dinv)
+        self.lmax = gershgorin_bound(self.A, self.dinv)
         self.lmax_c = lmax_estimate(self.Ac, self.dcinv)
         self.s, self.m = smooth_degree, coarse_degree
 

@@ -15,8 +15,11 @@
 //     per coarse block, summing its fine blocks in ascending order, so the result is
 //     deterministic), with a unit diagonal for dropped columns;
 //   * Chebyshev iteration (Saad, Iterative Methods for Sparse Linear Systems, Alg.
-//     12.1) on the interval [lmax / 30, lmax] of the Jacobi-scaled operator, lmax =
-//     min(1.2 x a 12-step power estimate from x_i = sin(1 + i), the Gershgorin bound);
+//     12.1) on the interval [lmax / 30, lmax] of the Jacobi-scaled operator; on the
+//     fine level lmax is the Gershgorin bound (the power estimate fell below the top of
+//     the spectrum of some tangents, and an interval that misses it makes M indefinite),
+//     on the coarse level min(1.2 x a 12-step power estimate from x_i = sin(1 + i), the
+//     Gershgorin bound) (the coarse polynomial's higher degree pays for a tight end);
 //   * one application z = M r: Chebyshev smoothing from 0, restriction of the residual,
 //     Chebyshev steps on A_c from 0, prolongation, Chebyshev smoothing continued from
 //     z.  Equal pre- and post-smoothers make M symmetric, so plain CG applies.
@@ -803,9 +806,8 @@ void amg_refresh(fem_handle *h, const T *values, const T *dinv, int precision, i
         hipLaunchKernelGGL((k_gersh_coarse<1, T>), dim3(kRedGrid), dim3(kThreads), 0, s, a.na, a.cptr, v.cvals,
                            v.cdinv, a.red);
     const double gc = host_max(a.red, kRedGrid, a.host_red, s);
-    a.lmax = lmax_bound<T>(
-        h, g.N, [&](const T *x, T *y, T alpha) { launch_spmv_sc<T>(h, values, x, y, alpha, T(0), nullptr, s); },
-        dinv, v.rc, v.d, gf, s);
+    if (!(gf > 0.0) || !std::isfinite(gf)) throw Error(FEM_ENAN, "preconditioner spectrum bound failed");
+    a.lmax = gf;
     a.lmax_c = lmax_bound<T>(
         h, M, [&](const T *x, T *y, T alpha) { coarse_spmv<T>(h, x, y, alpha, nullptr, s); }, v.cdinv, v.rcc, v.dc,
         gc, s);

@@ -180,6 +180,22 @@ def test_lmax_estimate_brackets_the_top_eigenvalue(n):
     assert lam_max <= lmax <= min(gersh, amg.LMAX_SAFETY * two_norm) * (1 + 1e-12), (lam_max, lmax, gersh)
 
 
+@pytest.mark.parametrize("n", [3, 4])
+def test_fine_interval_end_is_a_bound_of_the_spectrum(n):
+    """The fine smoother's interval ends at the Gershgorin bound: at or above the largest
+    eigenvalue of D^{-1} A (dense eigen-solve of D^{-1/2} A D^{-1/2}) and equal to the
+    largest scaled absolute row sum computed here from the dense matrix."""
+    A = _small_tangent(n)
+    dinv = 1.0 / A.diagonal()
+    Ad = A.toarray()
+    s = np.sqrt(dinv)
+    lam_max = np.linalg.eigvalsh(Ad * s[:, None] * s[None, :]).max()
+    gersh = (np.abs(Ad).sum(axis=1) * dinv).max()
+    b = amg.gershgorin_bound(A, dinv)
+    assert b == pytest.approx(gersh, rel=1e-14)
+    assert lam_max <= b * (1 + 1e-12)
+
+
 def test_lmax_estimate_is_capped_by_an_exact_gershgorin_bound():
     """Pairs [[1, 1], [1, 1]] scaled by different factors: D^{-1} A has eigenvalues 0 and
     2 and its Gershgorin bound is exactly 2; the power estimate reaches 2 from below, so
