@@ -100,9 +100,12 @@ enum { FEM_KRYLOV_CG = 0, FEM_KRYLOV_BICGSTAB = 1 };
  * Galerkin coarse operator on a rigid-body-mode coarse space of node aggregates (6
  * columns per aggregate; 1, the constant, when ndpn = 1) and Chebyshev steps on it.
  * The paper names the Jacobi-preconditioned solver as the bottleneck (Sec. 5, item 2);
- * this is the stronger preconditioner built on that remark.  The handle builds the
- * aggregates and prolongator once (first use) and keeps them with the coarse operator
- * of the latest tangent; see fem_amg_setup / fem_amg_export / fem_amg_apply below. */
+ * this is the stronger preconditioner built on that remark.  fem_amg_setup builds the
+ * aggregates and prolongator once per handle (solves with FEM_PRECOND_AMG refuse to run
+ * before it); the handle keeps them with the coarse operator of the latest tangent; see
+ * fem_amg_setup / fem_amg_export / fem_amg_apply below.  With FEM_PRECOND_JACOBI,
+ * BiCGSTAB runs on K D^{-1} (the scaling is folded into the solver's copy of the
+ * tangent), CG applies D^{-1} to its residual. */
 enum { FEM_PRECOND_JACOBI = 0, FEM_PRECOND_BLOCK_JACOBI = 1, FEM_PRECOND_AMG = 2 };
 
 typedef struct fem_handle fem_handle;
