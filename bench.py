@@ -119,7 +119,7 @@ def cpu_baseline(gpu_counts, method):
         u = np.zeros((p.n_nodes, 3))
         u[:, 0] = 0.16 * p.coords[:, 0]  # a stretched state like load step 4
         u = u.ravel()
-        t_res, t_asm, t_it, t_vjp = [], [], [], []
+        t_res, t_asm, t_it, t_vjp, t_spmv = [], [], [], [], []
         its_per_run = 5
         solver = orc.lib().orc_pcg if method == "cg" else orc.lib().orc_bicgstab
         for _ in range(3):
@@ -129,6 +129,9 @@ def cpu_baseline(gpu_counts, method):
             t0 = time.perf_counter()
             _, vals = orc.assemble(p, pat, u, None, None, residual=False)
             t_asm.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            orc.spmv(pat, vals, r)
+            t_spmv.append(time.perf_counter() - t0)
             x = np.zeros(pat.n)
             it_out, rel = ctypes.c_int(0), ctypes.c_double(0.0)
             t0 = time.perf_counter()
@@ -139,7 +142,8 @@ def cpu_baseline(gpu_counts, method):
             orc.vjp_theta(p, u, x)
             t_vjp.append(time.perf_counter() - t0)
             del vals
-    tr, ta, ti, tv = med(t_res), med(t_asm), med(t_it), med(t_vjp)
+    tr, ta, ti, tv, tm = med(t_res), med(t_asm), med(t_it), med(t_vjp), med(t_spmv)
+    small = small_cpu_timings()
     # Newton iteration: residual, tangent, the Krylov solve, the residual after the update;
     # gradient: tangent, the Krylov solve, one refinement residual per sweep, the VJP
     newton_ms = 1e3 * (2 * tr + ta + gpu_counts["newton_krylov_its"] * ti)
@@ -153,7 +157,52 @@ def cpu_baseline(gpu_counts, method):
                        f"iteration, {gpu_counts['adjoint_krylov_its']} in {gpu_counts['adjoint_sweeps']} adjoint "
                        f"sweeps); pattern build {t_pat:.1f} s not counted"),
             "newton_ms": newton_ms, "adjoint_ms": adjoint_ms,
-            "residual_s": tr, "assembly_s": ta, "krylov_iteration_ms": 1e3 * ti, "vjp_s": tv}
+            "residual_s": tr, "assembly_s": ta, "spmv_ms": 1e3 * tm, "krylov_iteration_ms": 1e3 * ti, "vjp_s": tv,
+            "host": {"model": model, "logical_cpus": ncpu, "sockets": host_sockets(), "threads_used": threads},
+            "single_thread_small_workloads": small}
+
+
+def host_sockets():
+    ids = set()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("physical id"):
+                ids.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    return len(ids) or None
+
+
+def small_cpu_timings():
+    """The oracle on one thread for the two small workloads (8^3 Poisson, 64x32x32
+    cantilever): tangent assembly, one SpMV and, for the Poisson cube, the whole Jacobi-CG
+    solve; medians of 3 runs."""
+    from oracle import oracle as orc
+    from paper_2212_00964_amd import inputs
+    med = lambda xs: float(np.median(xs))  # noqa: E731
+    out = {}
+    with orc.threads(1):
+        for name, p in (("poisson_8x8x8", inputs.workload(1)), ("cantilever_64x32x32", inputs.workload(2))):
+            pat = orc.Pattern(p)
+            F = orc.load_vector(p)
+            u = np.zeros(p.n_dofs)
+            ta, tm, ts = [], [], []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                r, vals = orc.assemble(p, pat, u, None, F)
+                ta.append(time.perf_counter() - t0)
+                t0 = time.perf_counter()
+                orc.spmv(pat, vals, r)
+                tm.append(time.perf_counter() - t0)
+                if name.startswith("poisson"):
+                    t0 = time.perf_counter()
+                    _, cg_its, _ = orc.krylov(pat, vals, -r, "cg", rtol=1e-10)
+                    ts.append(time.perf_counter() - t0)
+            out[name] = {"dofs": int(p.n_dofs), "nnz": int(pat.col_idx.size), "assembly_ms": 1e3 * med(ta),
+                         "spmv_ms": 1e3 * med(tm)}
+            if ts:  # the manufactured sine load is an eigenvector of the Jacobi-scaled operator here
+                out[name].update({"cg_solve_ms": 1e3 * med(ts), "cg_iterations": cg_its})
+    return out
 
 
 def refine_for(fem, prec, kry):
