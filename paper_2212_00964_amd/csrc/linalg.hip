@@ -188,12 +188,6 @@ __device__ __forceinline__ bool stopped(const KrylovScalars *sc) { return sc->co
 constexpr int kSpmvGroup = 32;
 constexpr int kMaxChunk = 1024;  // nodes per block staged in LDS
 
-// Chunk of the FP32-value / FP64-vector SpMV: at three blocks per CU the 100^3 mesh
-// gives each block 1,342 nodes, which one chunk of 1,344 covers (49 KB of LDS per
-// block; 237.5 against 239.7 us per launch with two chunks of 1,024 and 318).
-template <typename T, typename TV>
-constexpr int spmv_chunk() { return (sizeof(T) == 8 && sizeof(TV) == 4) ? 1344 : kMaxChunk; }
-
 // Nodes in flight per 32-lane group: as many as fit with the double-buffered loads
 // at an occupancy of four (FP32 values) or two (FP64 values) wavefronts per SIMD.
 // TV is the type of the stored values.  FP32 values under FP64 vectors (the mixed form
@@ -217,9 +211,8 @@ __global__ __launch_bounds__(kThreads, (spmv_waves<TV, T>())) void k_spmv_nodes(
     constexpr int G = kSpmvGroup;
     constexpr int GPB = kThreads / G;  // groups per block
     static_assert(G == 32 && (ND == 1 || ND == 3), "32-lane groups, 1 or 3 dofs per node");
-    constexpr int CHK = spmv_chunk<T, TV>();
-    __shared__ int64_t sptr[CHK + 1];
-    __shared__ T sy[CHK * ND];  // the chunk's results, written out at its end
+    __shared__ int64_t sptr[kMaxChunk + 1];
+    __shared__ T sy[kMaxChunk * ND];  // the chunk's results, written out at its end
     constexpr int NDOT = MODE == 2 ? 3 : MODE;  // (w0, y); MODE 2 also (y, y) and (w0, w0)
     __shared__ double sdot[MODE != 0 ? NDOT * kThreads : 1];  // per-thread dot terms (no registers in the node loop)
     if ((MODE != 0 || sc != nullptr) && stopped(sc)) return;  // MODE 0 with sc: inside a Krylov loop
@@ -231,8 +224,8 @@ __global__ __launch_bounds__(kThreads, (spmv_waves<TV, T>())) void k_spmv_nodes(
     const int grp = threadIdx.x / G;
     // after the group reduction, lanes 0, 8, 16 hold rows 0, 1, 2 of the node
     const int row = (lane & 7) == 0 && lane < 8 * ND ? lane / 8 : -1;
-    for (int64_t n0 = r0; n0 < r1; n0 += CHK) {
-        const int cnt = int(r1 - n0 < CHK ? r1 - n0 : CHK);
+    for (int64_t n0 = r0; n0 < r1; n0 += kMaxChunk) {
+        const int cnt = int(r1 - n0 < kMaxChunk ? r1 - n0 : kMaxChunk);
         __syncthreads();  // previous sub-chunk finished with sptr
         for (int i = threadIdx.x; i <= cnt; i += kThreads) sptr[i] = node_ptr[n0 + i];
         __syncthreads();
