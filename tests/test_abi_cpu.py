@@ -91,3 +91,24 @@ def test_build_pattern_refuses_a_collapsed_element():
     rc = fem.lib().fem_build_pattern(ctypes.byref(d), ctypes.byref(h), ctypes.byref(n), ctypes.byref(nnz))
     assert rc == -1 and not h.value
     assert b"lists a node twice" in fem.lib().fem_last_error()
+
+
+def test_roofline_byte_counts_of_the_benchmark():
+    """The algorithmic bytes the benchmark divides by: the 100^3 node-block SpMV
+    (245,438,109 values, 27,270,901 blocks of 3x3, 1,030,301 nodes, 3,090,903 dofs) with
+    FP32 values and FP32 or FP64 vectors and in FP64, counted by hand from those sizes,
+    and the minimum assembly bytes."""
+    import sys
+    from types import SimpleNamespace
+
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    nn, ne, n, nnz = 101 ** 3, 100 ** 3, 3 * 101 ** 3, (3 * 101 - 2) ** 3 * 9  # prod(3 n_i - 2) blocks
+    assert nnz == 245_438_109
+    prob = SimpleNamespace(nnz=nnz, n_dofs=n, spec=SimpleNamespace(ndpn=3, n_nodes=nn, n_elems=ne))
+    blocks = nnz // 9
+    assert bench.spmv_bytes(prob, 4) == nnz * 4 + blocks * 4 + (nn + 1) * 8 + 3 * n * 4 == 1_136_169_292
+    assert bench.spmv_bytes(prob, 4, 8) == 1_173_260_128
+    assert bench.spmv_bytes(prob, 8) == 2_155_012_564
+    assert bench.assembly_bytes(prob, 4) == nnz * 4 + n * 8 + ne * 8 + nn * 24 + ne * 32 == 1_071_206_884
