@@ -158,6 +158,27 @@ def test_two_level_needs_far_fewer_iterations_than_jacobi():
     prob.close()
 
 
+def test_two_level_keeps_its_advantage_on_a_late_load_step_of_an_elongated_block():
+    """The inverse workload's shape (2x1x1, stretched to 1.2 in 5 load steps) at reduced
+    size: the corrections of load step 5, from the state of load step 4, need at most a
+    third of Jacobi-CG's iterations with the two-level preconditioner (its fine smoother
+    must bound the top of the spectrum: an interval that misses it made the
+    preconditioner indefinite on the full-size block)."""
+    p, _ = gen.nh_inverse(40, 20, 20)
+    prob = fem.Problem(p, DEV)
+    g = prob.dirichlet_values
+    u4, _ = prob.newton_solve(dirichlet_values=0.8 * g, precision=fem.PREC_MIXED_V64, n_load_steps=4,
+                              newton_rtol=1e-9, krylov_rtol=1e-3)
+    o = dict(precision=1, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-3)
+    _, sj = prob.newton_solve(u0=u4, precond=fem.PRECOND_JACOBI, **o)
+    _, sa = prob.newton_solve(u0=u4, precond=fem.PRECOND_AMG, **o)
+    jac = list(sj.krylov_its[:sj.n_hist])
+    two = list(sa.krylov_its[:sa.n_hist])
+    assert sa.krylov_its_total * 3 <= sj.krylov_its_total, (two, jac)
+    assert max(two) * 3 <= max(jac), (two, jac)
+    prob.close()
+
+
 def test_two_level_option_errors():
     p = CASES["poisson-9-distorted"]
     prob = fem.Problem(p, DEV)

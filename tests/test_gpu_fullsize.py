@@ -359,3 +359,36 @@ def test_inverse_nh_200x100x100_gradient_against_patch_finite_differences():
     print(f"patch FD {fd} adjoint {adj} rel {np.abs(adj - fd) / np.abs(fd)}", flush=True)
     assert_parity(adj, fd, 1e-5, np.abs(adj - fd) / np.abs(fd))
     prob.close()
+
+
+def test_inverse_nh_200x100x100_two_level_on_load_step_5():
+    """The two-level preconditioner on the full-size inverse block at load step 5 (from
+    the state of load step 4): the fine smoother's interval must end above the top of the
+    Jacobi-scaled spectrum (checked against 100 power steps of D^{-1} K on the GPU), and
+    every Newton correction of the step needs at most 300 two-level CG iterations (an
+    interval that missed the top made the preconditioner indefinite here: 1,238-1,482
+    iterations per correction)."""
+    p, _ = gen.nh_inverse()
+    prob = fem.Problem(p, DEV)
+    g = prob.dirichlet_values
+    u4, _ = prob.newton_solve(dirichlet_values=0.8 * g, precision=fem.PREC_MIXED_V64, n_load_steps=4,
+                              newton_rtol=1e-9, krylov_rtol=1e-3)
+    _, K = prob.assemble(u4, residual=False)
+    diag_slot = prob.export_pattern(slot_map=False, transpose=False)["diag_slot"]
+    sq = torch.rsqrt(K[diag_slot])  # D^{-1/2}: D^{-1} K has the spectrum of D^{-1/2} K D^{-1/2}
+    x = torch.sin(1.0 + torch.arange(p.n_dofs, dtype=torch.float64, device=DEV))
+    lam = 0.0
+    for _ in range(100):  # ||S x|| / ||x|| of the symmetric S never exceeds its top eigenvalue
+        x = x / torch.linalg.norm(x)
+        y = sq * prob.spmv(K, sq * x)
+        lam = float(torch.linalg.norm(y))
+        x = y
+    del K
+    _, lm, _ = prob.amg_apply(u4, torch.ones(p.n_dofs, dtype=torch.float64, device=DEV), precision=fem.PREC_FP64)
+    assert lm[0] >= lam, (lm, lam)
+    u5, st = prob.newton_solve(u0=u4, precision=fem.PREC_MIXED, krylov=fem.CG, precond=fem.PRECOND_AMG,
+                               n_load_steps=1, newton_rtol=1e-9, krylov_rtol=1e-3, krylov_max_it=2000,
+                               newton_max_it=12)
+    its = list(st.krylov_its[:st.n_hist])
+    assert max(its) <= 300, its
+    prob.close()
