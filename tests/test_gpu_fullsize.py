@@ -266,6 +266,10 @@ def test_simp_120x60x30_gradient_closed_form_and_fd():
                       adjoint_rtol=1e-9)
     gm, _, _ = prob.adjoint_vjp(u, ft, opts=mixed)
     assert_parity(host(gm), gh, 1e-6)
+    mixed64 = prob.opts(precision=fem.PREC_MIXED_V64, krylov=fem.BICGSTAB, newton_rtol=1e-11, krylov_rtol=1e-3,
+                        adjoint_rtol=1e-9)
+    gm64, _, _ = prob.adjoint_vjp(u, ft, opts=mixed64)
+    assert_parity(host(gm64), gh, 1e-6)
     # One element moves J by ~1e-5 J here, so J must be accurate to ~1e-13: FP64 solves
     # warm-started from the base state, h = 1e-2 theta_e and a fourth-order stencil
     # (truncation O(h^4)); criterion norm-wise over the 20 elements as specified.

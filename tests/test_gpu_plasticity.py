@@ -127,7 +127,7 @@ def _gpu_path(prob, p, targets, n_steps, opts):
     return u, rec
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed64"])
 def test_loading_unloading_path_matches_oracle(precision):
     p = gen.j2_cylinder(4, 6, n_load_steps=3)
     targets = [p.dirichlet_values, np.zeros(p.n_dofs)]
@@ -136,9 +136,9 @@ def test_loading_unloading_path_matches_oracle(precision):
     if precision == "fp64":
         opts = prob.opts(precision=fem.PREC_FP64, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-12,
                          krylov_rtol=1e-10, newton_max_it=40)
-    else:  # FP32 tangent and Krylov (inner rtol 1e-5), FP64 residual
-        opts = prob.opts(precision=fem.PREC_MIXED, krylov=fem.CG, n_load_steps=1, newton_rtol=1e-10,
-                         krylov_rtol=1e-5, newton_max_it=60)
+    else:  # FP32 tangent, FP32 (or FP64) Krylov vectors (inner rtol 1e-5), FP64 residual
+        opts = prob.opts(precision=fem.PREC_MIXED if precision == "mixed" else fem.PREC_MIXED_V64, krylov=fem.CG,
+                         n_load_steps=1, newton_rtol=1e-10, krylov_rtol=1e-5, newton_max_it=60)
     u, rec = _gpu_path(prob, p, targets, 3, opts)
     tol = 1e-10 if precision == "fp64" else 1e-6
     assert_parity(u, u_ref, tol)
